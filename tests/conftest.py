@@ -1,0 +1,23 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session")
+def lib():
+    """The HIP library through its Python binding; skips when not built."""
+    from paper_1305_3625_amd import binding
+    try:
+        return binding.load()
+    except binding.LibraryNotBuilt as e:  # pragma: no cover
+        pytest.skip(str(e))
