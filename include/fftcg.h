@@ -1,0 +1,223 @@
+/*
+ * fftcg.h -- C ABI of the MI355X FFT-convolution conjugate-gradient solver.
+ *
+ * Problem (Gjerden, "Making the case of GPUs in courses on computational
+ * physics", Sec. 2 eqs. (1a)-(1c), (2); Sec. 3 eq. (3) and Listing 2):
+ *
+ *     A x = b,   A = diag(d) + C,
+ *     (C v)(i) = sum_{j in [0,L)^2} g_M((i - j) mod M) v(j),
+ *     g_M = inverse 2-D DFT of the multiplier ghat (M x M, real, even).
+ *
+ * Sec. 3 notes the Green's function depends only on the separation of two
+ * sites, so C is a convolution and is diagonal in Fourier space (eq. (3)):
+ * C v = F^{-1}(ghat . F v).  The periodic grid uses M = L; the zero-padded
+ * grid uses M = 2L and crops, which gives the linear convolution.  The paper
+ * treats the system as symmetric positive definite and solves it with
+ * unpreconditioned CG (Sec. 3 Listing 2, Sec. 4).  With a uniform fibre
+ * stiffness k, eq. (2) divided by k is this system with d = 1/k, b = D and
+ * x = f.
+ *
+ * Conventions for every call:
+ *   - Return value is a status code below; nothing throws, aborts or prints.
+ *   - Arguments are validated before any device work; invalid arguments
+ *     return FFTCG_EINVAL and leave every output untouched.
+ *   - Out-parameters are written only on FFTCG_OK (and on FFTCG_ENOCONV for
+ *     fftcg_solve / fftcg_poll, which return the last iterate).
+ *   - The library never frees caller memory.
+ *   - Grids are L x L, row-major, element (i1, i2) at index i1 * L + i2.
+ *   - "device pointer" means memory of the current HIP device (hipMalloc or a
+ *     torch CUDA/HIP tensor); "host pointer" means ordinary host memory.
+ *   - Streams are hipStream_t passed as void* (NULL = the default stream).
+ */
+#ifndef FFTCG_H
+#define FFTCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FFTCG_OK          0
+#define FFTCG_PENDING     1   /* fftcg_poll only: request still in flight   */
+#define FFTCG_EINVAL     -1   /* invalid argument or invalid input data     */
+#define FFTCG_ENOMEM     -2   /* device allocation failed / over budget     */
+#define FFTCG_ENOTSPD    -3   /* min ghat <= 0: A not positive definite     */
+#define FFTCG_ENOCONV    -4   /* maxit reached; x holds the last iterate    */
+#define FFTCG_EBREAKDOWN -5   /* p.q <= 0 or non-finite inside CG           */
+#define FFTCG_EAGAIN     -6   /* server queue full; retry later             */
+#define FFTCG_EDEVICE    -7   /* HIP runtime error / no usable gfx950 GPU   */
+#define FFTCG_ENOTFOUND  -8   /* unknown or already retired ticket          */
+#define FFTCG_ECANCELED  -9   /* request cancelled by server destruction    */
+
+/* ---- precision modes ----------------------------------------------------
+ * FFTCG_FP64 : every step in FP64.
+ * FFTCG_MIXED: the FFT passes, spectral multiply and the vectors r, p, q in
+ *              FP32; dot products accumulate in FP64; alpha/beta in FP64; an
+ *              FP64 true residual r = b - A x (FP64 operator) every
+ *              refresh period (50 iterations) and at candidate convergence,
+ *              with residual replacement.  Convergence is declared only at an
+ *              FP64 check.                                                  */
+#define FFTCG_FP64  0
+#define FFTCG_MIXED 1
+
+/* ---- engines (fftcg_plan_set_engine) -----------------------------------
+ * AUTO     : fused single-workgroup engine for M <= 128, multi-pass above.
+ * MULTIPASS: three HBM passes per product (row R2C, column FFT*ghat*IFFT,
+ *            row C2R + epilogue); available for M >= 8.
+ * FUSED    : one workgroup per solve, whole CG iteration in LDS; M <= 128.  */
+#define FFTCG_ENGINE_AUTO      0
+#define FFTCG_ENGINE_MULTIPASS 1
+#define FFTCG_ENGINE_FUSED     2
+
+typedef struct fftcg_plan_s*   fftcg_plan_t;
+typedef struct fftcg_server_s* fftcg_server_t;
+
+/* Per-solve report.  Relative quantities are relative to ||b||_2. */
+typedef struct {
+    int    status;              /* same as the call's return value           */
+    int    iterations;          /* CG iterations performed                   */
+    int    iterations_literal;  /* iteration count at the first FP64 check
+                                   where ||r||/||b|| <= tol held (-1: never)   */
+    int    checks;              /* FP64 true-residual checks performed       */
+    double true_relres;         /* ||b - A x||/||b|| at the last FP64 check  */
+    double error_bound;         /* certified bound on ||x - x*||/||x*||      */
+    double lambda_lb;           /* min(d) + min(ghat): lower eigenvalue bound */
+    double device_ms;           /* device time of the solve (HIP events)     */
+} fftcg_info;
+
+/* fftcg_plan -- build the spectral operator for one grid.
+ *   L               grid side, power of two, 2 <= L <= 2048.
+ *   padded          0: periodic grid, M = L.  1: zero-padded, M = 2L.
+ *   kernel_spectrum HOST pointer to M*M doubles, ghat[m*M + n] (m along the
+ *                   row index).  Copied; the caller keeps ownership.
+ *                   Must be finite and even in each index
+ *                   (ghat[m,n] == ghat[(M-m)%M, n] == ghat[m, (M-n)%M] to a
+ *                   relative 1e-12 of max|ghat|), else FFTCG_EINVAL; must have
+ *                   min > 0, else FFTCG_ENOTSPD (Sec. 3: CG needs SPD).
+ *   out             receives the plan handle.
+ * Sec. 3 / eq. (3): the static spectrum is transformed once at set-up; the
+ * normalisation 1/M^2 of the inverse transform (Listing 3) is folded into the
+ * stored spectrum.  The plan owns its device memory (current device).       */
+int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftcg_plan_t* out);
+
+/* Releases the plan.  FFTCG_EINVAL if a server still holds requests on it.  */
+int fftcg_plan_destroy(fftcg_plan_t plan);
+
+/* Selects the engine used by later calls on this plan (testing and tuning).
+ * FFTCG_EINVAL if the engine does not support this grid.                   */
+int fftcg_plan_set_engine(fftcg_plan_t plan, int engine);
+
+/* Reports L, M, padded, and the plan's device bytes (any pointer may be NULL). */
+int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* device_bytes);
+
+/* fftcg_apply -- y = (diag(d) + C) x, one operator product (Sec. 3 Listing 4
+ * plus the element-wise term that completes the left-hand side).
+ *   precision  FFTCG_FP64, or FFTCG_MIXED: x is rounded to FP32 and C is
+ *              applied in FP32; d*x is formed in FP64; y is FP64.
+ *   d, x, y    DEVICE pointers to L*L doubles.  y must not overlap x or d.
+ *   stream     hipStream_t; the call is stream-ordered and asynchronous.   */
+int fftcg_apply(fftcg_plan_t plan, int precision, const double* d,
+                const double* x, double* y, void* stream);
+
+/* fftcg_solve -- CG solve of (diag(d) + C) x = b (Sec. 3 Listing 2).
+ *   d, b       DEVICE pointers, L*L doubles; d >= 0 and finite, b finite
+ *              (checked on the device: FFTCG_EINVAL).
+ *   x0         DEVICE pointer to the start vector, or NULL for zero.  x may
+ *              equal x0 (warm start in place).
+ *   tol        residual rule ||b - A x||/||b|| <= tol, on an FP64 true
+ *              residual.  0 < tol < 1.
+ *   maxit      iteration cap, >= 1.  Reaching it returns FFTCG_ENOCONV with
+ *              x = last iterate and info filled.
+ *   x          DEVICE pointer, L*L doubles: the solution.
+ *   info       host pointer or NULL.
+ *   stream     hipStream_t used for all work; the call blocks until done.
+ * Stopping: the residual rule AND the certified rule
+ *   ||r|| <= tau * lambda_lb * ||x|| / (1 + tau),  lambda_lb = min d + min ghat,
+ * which guarantees ||x - x*||/||x*|| <= tau, with tau = 1e-10 (FP64) or 1e-8
+ * (MIXED).  b = 0 gives x = 0, FFTCG_OK and 0 iterations.                   */
+int fftcg_solve(fftcg_plan_t plan, int precision, const double* d,
+                const double* b, const double* x0, double tol, int maxit,
+                double* x, fftcg_info* info, void* stream);
+
+/* fftcg_loadstep -- one load step of the load-stepped workload: among the
+ * entries with d_i != 0, find i* = argmax x_i / t_i (FP64; ties to the
+ * smallest row-major index) and set d_{i*} = 0 (Sec. 2: a bond whose strain
+ * exceeds its threshold breaks).
+ *   x, t       DEVICE pointers, L*L doubles (t > 0).
+ *   d          DEVICE pointer, L*L doubles, updated in place.
+ *   index      HOST pointer: receives i*, or -1 if every d_i is 0.
+ * Blocks until the index is known.                                         */
+int fftcg_loadstep(fftcg_plan_t plan, const double* x, const double* t,
+                   double* d, int* index, void* stream);
+
+/* ---- continuous-batching server ---------------------------------------- */
+typedef struct {
+    size_t memory_budget;     /* bytes of device memory for request slots   */
+    int    max_slots;         /* slots per grid size (0: default 64)        */
+    int    chunk_iters;       /* CG iterations per step launch (0: 10)      */
+    int    refresh_period;    /* MIXED FP64 check period (0: 50)            */
+    int    queue_cap;         /* pending requests (0: 1<<20)                */
+    int    device;            /* HIP device ordinal                         */
+} fftcg_server_opts;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, failed, canceled;
+    size_t   bytes_in_use;
+    int      queued;
+    int      in_flight;
+} fftcg_server_stats;
+
+/* Starts the server's scheduler thread on opts->device.                    */
+int fftcg_server_create(const fftcg_server_opts* opts, fftcg_server_t* out);
+
+/* fftcg_submit -- enqueue one solve (same semantics as fftcg_solve).
+ *   d, b       HOST pointers, L*L doubles, copied before return.
+ *   x0         HOST pointer or NULL (zero start), copied before return.
+ *   ticket     receives the request id.
+ * FFTCG_EAGAIN when the queue is full; FFTCG_ENOMEM when one request's device
+ * footprint exceeds the whole budget; FFTCG_EINVAL for bad arguments or
+ * non-finite / negative data.  Never blocks on the GPU.                    */
+int fftcg_submit(fftcg_server_t srv, fftcg_plan_t plan, int precision,
+                 const double* d, const double* b, const double* x0,
+                 double tol, int maxit, uint64_t* ticket);
+
+/* fftcg_submit_sequence -- enqueue a load-stepped sequence: `steps` solves
+ * of the same grid; after each solve the load step (fftcg_loadstep rule)
+ * breaks one entry and the next solve is warm-started from the previous x.
+ *   t          HOST pointer, L*L thresholds, copied.
+ * fftcg_poll then returns the final x, and fftcg_poll_sequence the broken
+ * indices in order.                                                         */
+int fftcg_submit_sequence(fftcg_server_t srv, fftcg_plan_t plan, int precision,
+                          const double* d, const double* b, const double* t,
+                          double tol, int maxit, int steps, uint64_t* ticket);
+
+/* fftcg_poll -- FFTCG_PENDING, or the request's final status with x (HOST
+ * pointer, L*L doubles) and info copied out; the ticket is then retired and
+ * later polls return FFTCG_ENOTFOUND.  x or info may be NULL.              */
+int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info);
+
+/* fftcg_poll_sequence -- like fftcg_poll for a sequence ticket; also copies
+ * the broken indices (HOST pointer, `steps` ints) and the per-step iteration
+ * counts (HOST pointer, `steps` ints; may be NULL).                         */
+int fftcg_poll_sequence(fftcg_server_t srv, uint64_t ticket, double* x,
+                        int* broken, int* step_iters, fftcg_info* info);
+
+/* Counters of the server (host pointer).                                   */
+int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out);
+
+/* Stops the server; requests still queued or in flight end FFTCG_ECANCELED. */
+int fftcg_server_destroy(fftcg_server_t srv);
+
+/* Static description of a status code.                                     */
+const char* fftcg_strerror(int status);
+
+/* Library version string.                                                  */
+const char* fftcg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFTCG_H */

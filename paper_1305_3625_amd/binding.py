@@ -1,0 +1,290 @@
+"""ctypes binding of libfftcg.so (include/fftcg.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  Device arrays are torch tensors on the current HIP device
+(float64, contiguous, shape (L, L)); streams are torch streams.  When the
+library is not built, ``load()`` raises ``LibraryNotBuilt``; nothing here
+falls back to a CPU path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfftcg.so")
+
+OK, PENDING = 0, 1
+EINVAL, ENOMEM, ENOTSPD, ENOCONV, EBREAKDOWN = -1, -2, -3, -4, -5
+EAGAIN, EDEVICE, ENOTFOUND, ECANCELED = -6, -7, -8, -9
+FP64, MIXED = 0, 1
+ENGINE_AUTO, ENGINE_MULTIPASS, ENGINE_FUSED = 0, 1, 2
+
+STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "ENOCONV",
+                -5: "EBREAKDOWN", -6: "EAGAIN", -7: "EDEVICE", -8: "ENOTFOUND", -9: "ECANCELED"}
+
+# every symbol include/fftcg.h declares
+EXPORTS = [
+    "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_info",
+    "fftcg_apply", "fftcg_solve", "fftcg_loadstep",
+    "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
+    "fftcg_poll_sequence", "fftcg_server_get_stats", "fftcg_server_destroy",
+    "fftcg_strerror", "fftcg_version",
+]
+
+
+class LibraryNotBuilt(RuntimeError):
+    pass
+
+
+class FftcgError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({status})")
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("iterations_literal", ctypes.c_int), ("checks", ctypes.c_int),
+                ("true_relres", ctypes.c_double), ("error_bound", ctypes.c_double),
+                ("lambda_lb", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("chunk_iters", ctypes.c_int), ("refresh_period", ctypes.c_int),
+                ("queue_cap", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("canceled", ctypes.c_uint64), ("bytes_in_use", ctypes.c_size_t),
+                ("queued", ctypes.c_int), ("in_flight", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the library once and declares every signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise LibraryNotBuilt(f"{path} not built; run python -m paper_1305_3625_amd.build")
+    lib = ctypes.CDLL(path)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    U64P = ctypes.POINTER(ctypes.c_uint64)
+    sig = {
+        "fftcg_plan": (I, [I, I, P, ctypes.POINTER(P)]),
+        "fftcg_plan_destroy": (I, [P]),
+        "fftcg_plan_set_engine": (I, [P, I]),
+        "fftcg_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                                ctypes.POINTER(S)]),
+        "fftcg_apply": (I, [P, I, P, P, P, P]),
+        "fftcg_solve": (I, [P, I, P, P, P, D, I, P, ctypes.POINTER(Info), P]),
+        "fftcg_loadstep": (I, [P, P, P, P, ctypes.POINTER(I), P]),
+        "fftcg_server_create": (I, [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]),
+        "fftcg_submit": (I, [P, P, I, P, P, P, D, I, U64P]),
+        "fftcg_submit_sequence": (I, [P, P, I, P, P, P, D, I, I, U64P]),
+        "fftcg_poll": (I, [P, ctypes.c_uint64, P, ctypes.POINTER(Info)]),
+        "fftcg_poll_sequence": (I, [P, ctypes.c_uint64, P, P, P, ctypes.POINTER(Info)]),
+        "fftcg_server_get_stats": (I, [P, ctypes.POINTER(ServerStats)]),
+        "fftcg_server_destroy": (I, [P]),
+        "fftcg_strerror": (ctypes.c_char_p, [I]),
+        "fftcg_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().fftcg_strerror(status).decode()
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 torch tensor on a HIP device."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a tensor on the GPU")
+    if t.dtype.is_floating_point and t.element_size() != 8:
+        raise ValueError("expected float64")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host(a):
+    """Pointer to a C-contiguous float64 numpy array (host)."""
+    import numpy as np
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Plan:
+    """fftcg_plan: spectral operator of one grid (L, padded, ghat)."""
+
+    def __init__(self, L: int, padded: int, ghat):
+        import numpy as np
+        lib = load()
+        g = np.ascontiguousarray(ghat, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = lib.fftcg_plan(int(L), int(padded), g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+        if st != OK:
+            raise FftcgError(st, "fftcg_plan")
+        self.h = h
+        self.L, self.padded = int(L), int(padded)
+        self.M = 2 * self.L if padded else self.L
+
+    def set_engine(self, engine: int):
+        st = load().fftcg_plan_set_engine(self.h, engine)
+        if st != OK:
+            raise FftcgError(st, "fftcg_plan_set_engine")
+
+    def info(self):
+        L, M, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        b = ctypes.c_size_t()
+        st = load().fftcg_plan_info(self.h, ctypes.byref(L), ctypes.byref(M), ctypes.byref(p), ctypes.byref(b))
+        if st != OK:
+            raise FftcgError(st, "fftcg_plan_info")
+        return dict(L=L.value, M=M.value, padded=p.value, device_bytes=b.value)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            st = load().fftcg_plan_destroy(self.h)
+            if st != OK:
+                raise FftcgError(st, "fftcg_plan_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                load().fftcg_plan_destroy(self.h)
+        except Exception:
+            pass
+
+    # -- device calls ------------------------------------------------------
+    def apply(self, d, x, y, precision=FP64, stream=None):
+        st = load().fftcg_apply(self.h, precision, _ptr(d), _ptr(x), _ptr(y), _stream(stream))
+        if st != OK:
+            raise FftcgError(st, "fftcg_apply")
+        return y
+
+    def solve(self, d, b, x, x0=None, tol=1e-10, maxit=10000, precision=FP64, stream=None,
+              raise_on_error=True):
+        info = Info()
+        st = load().fftcg_solve(self.h, precision, _ptr(d), _ptr(b), _ptr(x0), float(tol), int(maxit),
+                                _ptr(x), ctypes.byref(info), _stream(stream))
+        if st not in (OK,) and raise_on_error and st != ENOCONV:
+            raise FftcgError(st, "fftcg_solve")
+        out = info.as_dict()
+        out["status"] = st
+        return out
+
+    def loadstep(self, x, t, d, stream=None):
+        idx = ctypes.c_int(-2)
+        st = load().fftcg_loadstep(self.h, _ptr(x), _ptr(t), _ptr(d), ctypes.byref(idx), _stream(stream))
+        if st != OK:
+            raise FftcgError(st, "fftcg_loadstep")
+        return idx.value
+
+
+@dataclass
+class Result:
+    status: int
+    x: object
+    info: dict
+
+
+class Server:
+    """fftcg_server_*: continuous-batching solve server (host arrays)."""
+
+    def __init__(self, memory_budget=4 << 30, max_slots=0, chunk_iters=0, refresh_period=0,
+                 queue_cap=0, device=0):
+        lib = load()
+        o = ServerOpts(memory_budget, max_slots, chunk_iters, refresh_period, queue_cap, device)
+        h = ctypes.c_void_p()
+        st = lib.fftcg_server_create(ctypes.byref(o), ctypes.byref(h))
+        if st != OK:
+            raise FftcgError(st, "fftcg_server_create")
+        self.h = h
+
+    def submit(self, plan: Plan, d, b, x0=None, tol=1e-8, maxit=10000, precision=MIXED):
+        dd, dp = _host(d)
+        bb, bp = _host(b)
+        xp = None
+        if x0 is not None:
+            xx, xp = _host(x0)
+        t = ctypes.c_uint64()
+        st = load().fftcg_submit(self.h, plan.h, precision, dp, bp, xp, float(tol), int(maxit), ctypes.byref(t))
+        return st, t.value
+
+    def submit_sequence(self, plan: Plan, d, b, t, steps, tol=1e-8, maxit=10000, precision=MIXED):
+        dd, dp = _host(d)
+        bb, bp = _host(b)
+        tt, tp = _host(t)
+        tk = ctypes.c_uint64()
+        st = load().fftcg_submit_sequence(self.h, plan.h, precision, dp, bp, tp, float(tol), int(maxit),
+                                          int(steps), ctypes.byref(tk))
+        return st, tk.value
+
+    def poll(self, ticket, L):
+        import numpy as np
+        x = np.empty((L, L))
+        info = Info()
+        st = load().fftcg_poll(self.h, ctypes.c_uint64(ticket), x.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(info))
+        return Result(st, x if st in (OK, ENOCONV) else None, info.as_dict())
+
+    def poll_sequence(self, ticket, L, steps):
+        import numpy as np
+        x = np.empty((L, L))
+        broken = np.empty(steps, dtype=np.int32)
+        iters = np.empty(steps, dtype=np.int32)
+        info = Info()
+        st = load().fftcg_poll_sequence(self.h, ctypes.c_uint64(ticket), x.ctypes.data_as(ctypes.c_void_p),
+                                        broken.ctypes.data_as(ctypes.c_void_p),
+                                        iters.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info))
+        if st in (OK, ENOCONV):
+            return Result(st, (x, broken, iters), info.as_dict())
+        return Result(st, None, info.as_dict())
+
+    def stats(self):
+        s = ServerStats()
+        st = load().fftcg_server_get_stats(self.h, ctypes.byref(s))
+        if st != OK:
+            raise FftcgError(st, "fftcg_server_get_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            load().fftcg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

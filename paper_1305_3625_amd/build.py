@@ -1,0 +1,89 @@
+"""Builds libfftcg.so (HIP, gfx950 only) in-tree.
+
+Every source under ``csrc/`` is compiled with hipcc for ``--offload-arch=gfx950``;
+the multi-pass engine source is compiled once per grid size and boundary
+condition.  Objects go to ``_build/`` at the repository root and the library
+to ``paper_1305_3625_amd/libfftcg.so``.
+
+    python -m paper_1305_3625_amd.build [--jobs N]
+"""
+
+from __future__ import annotations
+
+import argparse
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INC = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libfftcg.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+CXXFLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # packed FP32 instructions stay off (hand-written or compiler-made)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
+    f"-I{INC}", f"-I{CSRC}",
+]
+
+ENGINE_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)] + \
+               [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)]
+
+SOURCES = ["fftcg_host.cpp", "common.hip", "fused.hip", "server.cpp"]
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l and
+                    "target-feature" not in l)
+    if p.returncode != 0:
+        raise RuntimeError("compile failed: " + " ".join(cmd) + "\n" + out)
+    return out
+
+
+def _obj(name):
+    return os.path.join(BUILD, name + ".o")
+
+
+def _jobs():
+    for s in SOURCES:
+        src = os.path.join(CSRC, s)
+        lang = ["-x", "hip"] if s.endswith(".cpp") else []
+        yield [HIPCC, *CXXFLAGS, *lang, "-c", src, "-o", _obj(os.path.splitext(s)[0])]
+    for m, pad in ENGINE_SIZES:
+        yield [HIPCC, *CXXFLAGS, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", "-c",
+               os.path.join(CSRC, "engine_inst.hip"), "-o", _obj(f"engine_{m}_{pad}")]
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    cmds = list(_jobs())
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for out in ex.map(_run, cmds):
+            if verbose and out.strip():
+                print(out)
+    objs = [c[-1] for c in cmds]
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("-v", "--verbose", action="store_true")
+    a = ap.parse_args(argv)
+    print(build(a.jobs, a.verbose))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,97 @@
+// Size-independent kernels: FP32 copy of the diagonal, and the load-step
+// argmax (Sec. 2: after each solve the bond with the largest strain relative
+// to its threshold breaks).
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "fftcg_dev.hpp"
+
+namespace fftcg {
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
+// (value, index) argmax with ties to the smaller index; entries with d == 0
+// are excluded (value -inf, index n).
+struct VI {
+    double v;
+    int i;
+};
+__device__ __forceinline__ VI better(VI a, VI b) {
+    if (a.v > b.v) return a;
+    if (b.v > a.v) return b;
+    return a.i <= b.i ? a : b;
+}
+__device__ __forceinline__ VI wave_best(VI a) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        VI b;
+        b.v = __shfl_xor(a.v, o, 64);
+        b.i = __shfl_xor(a.i, o, 64);
+        a = better(a, b);
+    }
+    return a;
+}
+constexpr int LS_NT = 256;
+
+__device__ VI block_best(VI a) {
+    __shared__ double sv[LS_NT / 64];
+    __shared__ int si[LS_NT / 64];
+    a = wave_best(a);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = a.v;
+        si[threadIdx.x >> 6] = a.i;
+    }
+    __syncthreads();
+    VI r{sv[0], si[0]};
+    for (int w = 1; w < LS_NT / 64; ++w) r = better(r, VI{sv[w], si[w]});
+    return r;
+}
+
+__global__ void __launch_bounds__(LS_NT)
+    k_loadstep_partial(const double* __restrict__ x, const double* __restrict__ t,
+                       const double* __restrict__ d, int n, double* __restrict__ pv, int* __restrict__ pi) {
+    VI best{-INFINITY, n};
+    for (int i = blockIdx.x * LS_NT + threadIdx.x; i < n; i += gridDim.x * LS_NT) {
+        if (d[i] != 0.0) best = better(best, VI{x[i] / t[i], i});
+    }
+    best = block_best(best);
+    if (threadIdx.x == 0) {
+        pv[blockIdx.x] = best.v;
+        pi[blockIdx.x] = best.i;
+    }
+}
+
+__global__ void __launch_bounds__(LS_NT)
+    k_loadstep_final(const double* __restrict__ pv, const int* __restrict__ pi, int nb, int n,
+                     double* __restrict__ d, int* __restrict__ out) {
+    VI best{-INFINITY, n};
+    for (int b = threadIdx.x; b < nb; b += LS_NT) best = better(best, VI{pv[b], pi[b]});
+    best = block_best(best);
+    if (threadIdx.x == 0) {
+        const int idx = best.i < n ? best.i : -1;
+        if (idx >= 0) d[idx] = 0.0;
+        out[0] = idx;
+    }
+}
+
+void launch_to_f32(const double* src, float* dst, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+}
+
+int loadstep_blocks(int n) {
+    int b = (n + LS_NT * 16 - 1) / (LS_NT * 16);
+    return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+void launch_loadstep(const double* x, const double* t, double* d, int n, double* pv, int* pi, int* out,
+                     hipStream_t s) {
+    const int nb = loadstep_blocks(n);
+    hipLaunchKernelGGL(k_loadstep_partial, dim3(nb), dim3(LS_NT), 0, s, x, t, d, n, pv, pi);
+    hipLaunchKernelGGL(k_loadstep_final, dim3(1), dim3(LS_NT), 0, s, pv, pi, nb, n, d, out);
+}
+
+}  // namespace fftcg

@@ -1,0 +1,14 @@
+// Launchers of the size-independent kernels (common.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fftcg {
+
+void launch_to_f32(const double* src, float* dst, int n, hipStream_t s);
+int loadstep_blocks(int n);
+// argmax over d != 0 of x / t (ties to the smaller index), d[i*] = 0,
+// *out = i* or -1.  pv / pi hold loadstep_blocks(n) partials.
+void launch_loadstep(const double* x, const double* t, double* d, int n, double* pv, int* pi, int* out,
+                     hipStream_t s);
+
+}  // namespace fftcg

@@ -1,0 +1,40 @@
+// Host-side view of one compiled engine (one FFT grid size M and boundary
+// condition).  Each engine_inst_<M>_<pad>.o fills one EngineOps with
+// launchers for the multi-pass kernels of that size.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "fftcg_types.hpp"
+
+namespace fftcg {
+
+template <typename T>
+struct cx;
+
+struct PlanTabs {
+    const void* tw32;   // cx<float>[M]
+    const void* ghq32;  // float, tile layout of the FP32 column pass
+    const void* ghN32;  // float[M/2 + 1]
+    const void* tw64;   // cx<double>[M]
+    const void* ghq64;  // double, tile layout of the FP64 column pass
+    const void* ghN64;  // double[M/2 + 1]
+};
+
+struct EngineOps {
+    int M, pad, L;
+    int tt32, tt64;          // columns per tile of the column pass
+    int rowblk32, rowblk64;  // blocks of the row passes (= partial counts)
+    int g4;                  // blocks of the update kernel (= r.r partial count)
+    // y = d x + C x, precision 0 = FP64, 1 = FP32 operator
+    void (*apply)(int prec, const PlanTabs& t, const double* d, const double* x, double* y,
+                  void* W, hipStream_t s);
+    // one CG iteration for nslots slots (row_fwd, col, row_inv, update)
+    void (*iter)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
+                 hipStream_t s);
+    // one FP64 check (row_fwd, col, row_inv on x, then the finaliser)
+    void (*check)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
+                  hipStream_t s);
+};
+
+const EngineOps* find_engine(int M, int pad);
+
+}  // namespace fftcg

@@ -1,0 +1,129 @@
+// Instantiates the multi-pass engine for one grid; compiled once per
+// (FFTCG_M, FFTCG_PAD) by the build script.
+#include <string.h>
+
+#include "engine.hpp"
+#include "fftcg_kernels.hpp"
+
+#ifndef FFTCG_M
+#error "FFTCG_M must be defined"
+#endif
+#ifndef FFTCG_PAD
+#error "FFTCG_PAD must be defined"
+#endif
+
+#define FFTCG_CAT2(a, b, c) a##b##_##c
+#define FFTCG_CAT(a, b, c) FFTCG_CAT2(a, b, c)
+#define FFTCG_OPS_FN FFTCG_CAT(fftcg_engine_ops_, FFTCG_M, FFTCG_PAD)
+
+namespace fftcg {
+namespace {
+
+constexpr int M = FFTCG_M;
+constexpr int PAD = FFTCG_PAD;
+template <typename T>
+using G = Geo<T, M, PAD>;
+constexpr int LL = G<float>::L;
+constexpr int UPD_NT = 256;
+constexpr int g4_blocks() {
+    return cmax(1, cmin(1024, LL * LL / 1024));
+}
+
+template <typename T>
+Tab<T> tab_of(const PlanTabs& t);
+template <>
+Tab<float> tab_of<float>(const PlanTabs& t) {
+    return Tab<float>{(const cx<float>*)t.tw32, (const float*)t.ghq32, (const float*)t.ghN32};
+}
+template <>
+Tab<double> tab_of<double>(const PlanTabs& t) {
+    return Tab<double>{(const cx<double>*)t.tw64, (const double*)t.ghq64, (const double*)t.ghN64};
+}
+
+template <typename T>
+void apply_t(const PlanTabs& pt, const double* d, const double* x, double* y, void* W, hipStream_t s) {
+    constexpr int RT = G<T>::ROW_THREADS, CT = G<T>::COL_THREADS;
+    ByVal sv;
+    memset(&sv.s, 0, sizeof(SlotDesc));
+    sv.s.d = d;
+    sv.s.x = const_cast<double*>(x);
+    sv.s.y = y;
+    sv.s.W = W;
+    sv.s.active = 1;
+    const Tab<T> tab = tab_of<T>(pt);
+    hipLaunchKernelGGL((k_row_fwd<T, M, PAD, ProApply<T>, ByVal, RT>), dim3(G<T>::ROW_BLOCKS), dim3(RT), 0, s,
+                       tab, sv, 0, 0);
+    hipLaunchKernelGGL((k_col<T, M, PAD, GateAlways, ByVal, CT>), dim3(G<T>::NTILE), dim3(CT), 0, s, tab, sv);
+    hipLaunchKernelGGL((k_row_inv<T, M, PAD, EpiApply<T>, ByVal, RT>), dim3(G<T>::ROW_BLOCKS), dim3(RT), 0, s,
+                       tab, sv, 0);
+}
+
+void apply_fn(int prec, const PlanTabs& pt, const double* d, const double* x, double* y, void* W,
+              hipStream_t s) {
+    if (prec == 0)
+        apply_t<double>(pt, d, x, y, W, s);
+    else
+        apply_t<float>(pt, d, x, y, W, s);
+}
+
+template <typename W, typename XA>
+void iter_t(const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS;
+    const ByPtr sp{slots};
+    const Tab<W> tab = tab_of<W>(pt);
+    hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProCG<W, XA, RT>, ByPtr, RT>), dim3(G<W>::ROW_BLOCKS, nslots),
+                       dim3(RT), 0, s, tab, sp, g4_blocks(), stride);
+    hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE, nslots), dim3(CT), 0, s, tab,
+                       sp);
+    hipLaunchKernelGGL((k_row_inv<W, M, PAD, EpiCG<W>, ByPtr, RT>), dim3(G<W>::ROW_BLOCKS, nslots), dim3(RT), 0,
+                       s, tab, sp, stride);
+    hipLaunchKernelGGL((k_update<W, UPD_NT>), dim3(g4_blocks(), nslots), dim3(UPD_NT), 0, s, sp, LL * LL,
+                       G<W>::ROW_BLOCKS, stride);
+}
+
+void iter_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    if (prec == 0)
+        iter_t<double, double>(pt, slots, nslots, stride, s);
+    else
+        iter_t<float, float>(pt, slots, nslots, stride, s);
+}
+
+template <typename W>
+void check_t(const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    constexpr int RT = G<double>::ROW_THREADS, CT = G<double>::COL_THREADS;
+    const ByPtr sp{slots};
+    const Tab<double> tab = tab_of<double>(pt);
+    hipLaunchKernelGGL((k_row_fwd<double, M, PAD, ProCheck<W, RT>, ByPtr, RT>),
+                       dim3(G<double>::ROW_BLOCKS, nslots), dim3(RT), 0, s, tab, sp, 0, stride);
+    hipLaunchKernelGGL((k_col<double, M, PAD, GateCheck, ByPtr, CT>), dim3(G<double>::NTILE, nslots), dim3(CT), 0,
+                       s, tab, sp);
+    hipLaunchKernelGGL((k_row_inv<double, M, PAD, EpiCheck<W>, ByPtr, RT>), dim3(G<double>::ROW_BLOCKS, nslots),
+                       dim3(RT), 0, s, tab, sp, stride);
+    hipLaunchKernelGGL((k_check_final<256>), dim3(1, nslots), dim3(256), 0, s, sp, G<double>::ROW_BLOCKS,
+                       g4_blocks(), stride);
+}
+
+void check_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    if (prec == 0)
+        check_t<double>(pt, slots, nslots, stride, s);
+    else
+        check_t<float>(pt, slots, nslots, stride, s);
+}
+
+const EngineOps kOps = {M,
+                        PAD,
+                        LL,
+                        G<float>::TT,
+                        G<double>::TT,
+                        G<float>::ROW_BLOCKS,
+                        G<double>::ROW_BLOCKS,
+                        g4_blocks(),
+                        &apply_fn,
+                        &iter_fn,
+                        &check_fn};
+
+}  // namespace
+
+const EngineOps* FFTCG_OPS_FN() { return &kOps; }
+
+}  // namespace fftcg

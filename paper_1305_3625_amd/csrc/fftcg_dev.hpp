@@ -1,0 +1,263 @@
+// Device building blocks of the FFT engine for gfx950 (wave64).
+//
+// * cx<T>        complex value in registers (T = float or double).
+// * dft<R,DIR>   radix-R DFT (R = 1, 2, 4, 8, 16) on R registers, as radix-2
+//                decimation-in-frequency layers with compile-time twiddles;
+//                HALF_IN skips the upper half of the inputs (known zeros).
+// * stages<...>  Stockham self-sorting FFT of length N held by N/E threads of
+//                E = min(N, 16) values each.  Butterfly b of a radix-R stage
+//                reads positions b + r N/R and writes
+//                (b / Ns) Ns R + b % Ns + r Ns, so the output is in natural
+//                order and no bit-reversal pass exists.  Between stages the
+//                values go through LDS with a padded layout.
+// * block reductions with a fixed summation order (wave shuffle tree, then
+//   wave partials summed in index order), so every run gives bitwise the
+//   same scalars.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftcg {
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mkc(T a, T b) {
+    cx<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mkc(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mkc(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return mkc(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conjc(cx<T> a) { return mkc(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> scalec(cx<T> a, T s) { return mkc(a.x * s, a.y * s); }
+
+// a * exp(DIR * 2 pi i * k / 16); folds to a few adds for constant k.
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> rot16(cx<T> a, int k) {
+    const T c1 = T(0.92387953251128675613);  // cos(pi/8)
+    const T c2 = T(0.70710678118654752440);  // cos(pi/4)
+    const T c3 = T(0.38268343236508977173);  // cos(3pi/8)
+    const T d = T(DIR);
+    switch (k & 15) {
+        case 0: return a;
+        case 4: return DIR > 0 ? mkc(-a.y, a.x) : mkc(a.y, -a.x);
+        case 8: return mkc(-a.x, -a.y);
+        case 12: return DIR > 0 ? mkc(a.y, -a.x) : mkc(-a.y, a.x);
+        case 2: return mkc(c2 * (a.x - d * a.y), c2 * (d * a.x + a.y));
+        case 6: return mkc(c2 * (-a.x - d * a.y), c2 * (d * a.x - a.y));
+        case 10: return mkc(c2 * (-a.x + d * a.y), c2 * (-d * a.x - a.y));
+        case 14: return mkc(c2 * (a.x + d * a.y), c2 * (-d * a.x + a.y));
+        default: break;
+    }
+    T c, s;
+    switch (k & 15) {
+        case 1: c = c1; s = c3; break;
+        case 3: c = c3; s = c1; break;
+        case 5: c = -c3; s = c1; break;
+        case 7: c = -c1; s = c3; break;
+        case 9: c = -c1; s = -c3; break;
+        case 11: c = -c3; s = -c1; break;
+        case 13: c = c3; s = -c1; break;
+        default: c = c1; s = -c3; break;  // 15
+    }
+    s = d * s;
+    return mkc(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+__host__ __device__ constexpr int brev(int i, int bits) {
+    return bits == 0 ? 0 : (((i & 1) << (bits - 1)) | brev(i >> 1, bits - 1));
+}
+
+// In-register radix-R DFT, X[k] = sum_r v[r] exp(DIR 2 pi i r k / R).
+template <typename T, int R, int DIR, bool HALF_IN>
+__device__ __forceinline__ void dft(cx<T>* v) {
+    if constexpr (R == 1) {
+        return;
+    } else {
+        cx<T> t[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) t[i] = v[i];
+#pragma unroll
+        for (int lh = ilog2c(R) - 1; lh >= 0; --lh) {
+            const int h = 1 << lh;
+#pragma unroll
+            for (int g = 0; g < R; g += 2 * h) {
+#pragma unroll
+                for (int i = 0; i < h; ++i) {
+                    const int k16 = i * (16 / (2 * h));
+                    cx<T> a = t[g + i];
+                    if (HALF_IN && h == R / 2) {
+                        t[g + i] = a;
+                        t[g + i + h] = rot16<T, DIR>(a, k16);
+                    } else {
+                        cx<T> b = t[g + i + h];
+                        t[g + i] = a + b;
+                        t[g + i + h] = rot16<T, DIR>(a - b, k16);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[brev(i, ilog2c(R))] = t[i];
+    }
+}
+
+// ---- radix plans ----------------------------------------------------------
+// Forward order: 16, 16, ..., then the remainder radix (2, 4 or 8).
+// Reversed order: remainder first.  Lengths below 16 use one stage.
+__host__ __device__ constexpr int fft_elems(int N) { return N >= 16 ? 16 : N; }
+__host__ __device__ constexpr int fft_nstages(int N) {
+    return N <= 1 ? 0 : (N < 16 ? 1 : ilog2c(N) / 4 + (ilog2c(N) % 4 ? 1 : 0));
+}
+__host__ __device__ constexpr int fft_radix(int N, bool rev, int s) {
+    // stage s of the plan
+    return N < 16 ? N
+                  : (ilog2c(N) % 4 == 0
+                         ? 16
+                         : (rev ? (s == 0 ? (1 << (ilog2c(N) % 4)) : 16)
+                                : (s == fft_nstages(N) - 1 ? (1 << (ilog2c(N) % 4)) : 16)));
+}
+__host__ __device__ constexpr int fft_ns(int N, bool rev, int s) {
+    return s == 0 ? 1 : fft_ns(N, rev, s - 1) * fft_radix(N, rev, s - 1);
+}
+
+// LDS layout: complex word w = pos * TT + col, stored at w + (w >> SH) * PADW.
+template <typename T, int TT, int SH, int PADW>
+struct LdsLay {
+    cx<T>* base;
+    int col;
+    __device__ __forceinline__ int phys(int pos) const {
+        int w = pos * TT + col;
+        return w + (w >> SH) * PADW;
+    }
+    __device__ __forceinline__ void st(int pos, cx<T> v) const { base[phys(pos)] = v; }
+    __device__ __forceinline__ cx<T> ld(int pos) const { return base[phys(pos)]; }
+    static constexpr int words(int n) { return n * TT + ((n * TT) >> SH) * PADW + PADW; }
+};
+
+// Runs stages S.. of the length-N transform held by this thread (index j of
+// N/E threads).  On entry v[u R + r] holds position (j + u P) + r N / R_S.
+// On exit v[u R_last + r] holds position (j + u P) + r N / R_last.
+// tw[m] = exp(-2 pi i m / MTAB); DIR = -1 forward, +1 inverse.
+template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, int S, class Lay>
+__device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j,
+                                       const cx<T>* __restrict__ tw) {
+    constexpr int E = fft_elems(N);
+    constexpr int P = N / E;
+    constexpr int R = fft_radix(N, REV, S);
+    constexpr int NS = fft_ns(N, REV, S);
+    constexpr int NB = E / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int b = j + u * P;
+        if constexpr (NS > 1) {
+            const int k = b & (NS - 1);
+            constexpr int STEP = MTAB / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[k * r * STEP];
+                if (DIR > 0) w.y = -w.y;
+                v[u * R + r] = cmul(v[u * R + r], w);
+            }
+        }
+        dft<T, R, DIR, HALF_IN && S == 0>(v + u * R);
+    }
+    if constexpr (S + 1 < fft_nstages(N)) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int b = j + u * P;
+            const int base = (b / NS) * NS * R + (b & (NS - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) lay.st(base + r * NS, v[u * R + r]);
+        }
+        __syncthreads();
+        constexpr int R2 = fft_radix(N, REV, S + 1);
+        constexpr int NB2 = E / R2;
+#pragma unroll
+        for (int u = 0; u < NB2; ++u) {
+            const int b = j + u * P;
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[u * R2 + r] = lay.ld(b + r * (N / R2));
+        }
+        __syncthreads();
+        stages<T, N, MTAB, DIR, REV, HALF_IN, S + 1, Lay>(v, lay, j, tw);
+    }
+}
+
+// Full transform (all stages).  Length 1 is the identity.
+template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, class Lay>
+__device__ __forceinline__ void fft_run(cx<T>* v, const Lay& lay, int j,
+                                        const cx<T>* __restrict__ tw) {
+    if constexpr (fft_nstages(N) > 0) stages<T, N, MTAB, DIR, REV, HALF_IN, 0, Lay>(v, lay, j, tw);
+}
+
+// ---- reductions -----------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum over the block of NT threads; result valid in every thread.  sh must
+// hold NT/64 doubles.  Fixed order: shuffle tree, then waves in index order.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    if constexpr (NT < 64) {
+#pragma unroll
+        for (int o = NT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, NT);
+        return v;
+    }
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < (NT + 63) / 64; ++w) s += sh[w];
+    return s;
+}
+template <int NT>
+__device__ __forceinline__ double block_min(double v, double* sh) {
+    if constexpr (NT < 64) {
+#pragma unroll
+        for (int o = NT / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, NT));
+        return v;
+    }
+    v = wave_min(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = sh[0];
+#pragma unroll
+    for (int w = 1; w < (NT + 63) / 64; ++w) s = fmin(s, sh[w]);
+    return s;
+}
+
+// Sum of n partials in a fixed order (thread t takes t, t+NT, ...).
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+    return block_sum<NT>(s, sh);
+}
+
+}  // namespace fftcg

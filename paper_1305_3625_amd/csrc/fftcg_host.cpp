@@ -1,0 +1,577 @@
+// C ABI: plans, operator products, device-resident CG solves, load steps.
+//
+// Sec. 3 of the paper: the CG loop of Listing 2 runs with every product
+// evaluated by FFT (eq. (3)); Sec. 4: the GPU does almost all the work and
+// reports only a few values to the CPU when the solver has finished.  Here a
+// solve is a stream of kernel launches: an initial FP64 residual check, then
+// chunks of CG iterations each followed by a (usually empty) FP64 check.  The
+// CG scalars and the stop decision live in device memory; the host reads one
+// pinned status word per chunk, two chunks behind the device so the GPU never
+// waits for the host.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "engine.hpp"
+#include "fftcg.h"
+#include "fftcg_internal.hpp"
+#include "fused.hpp"
+
+namespace fftcg {
+
+// ---- engine registry --------------------------------------------------------
+#define FFTCG_DECL(M, P) const EngineOps* fftcg_engine_ops_##M##_##P();
+#define FFTCG_SIZES(X)                                                                          \
+    X(2, 0) X(4, 0) X(8, 0) X(16, 0) X(32, 0) X(64, 0) X(128, 0) X(256, 0) X(512, 0) X(1024, 0) \
+        X(2048, 0) X(4096, 0) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(128, 1) X(256, 1)    \
+            X(512, 1) X(1024, 1) X(2048, 1) X(4096, 1)
+FFTCG_SIZES(FFTCG_DECL)
+#undef FFTCG_DECL
+
+const EngineOps* find_engine(int M, int pad) {
+#define FFTCG_CASE(MM, PP) \
+    if (M == MM && pad == PP) return fftcg_engine_ops_##MM##_##PP();
+    FFTCG_SIZES(FFTCG_CASE)
+#undef FFTCG_CASE
+    return nullptr;
+}
+
+// ---- helpers ----------------------------------------------------------------
+static bool ispow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// cos and sin of 2 pi r / M with the argument reduced exactly: integer
+// quadrant and octant folding, then the library functions on [0, pi/4].
+void cos_sin_2pi(long r, long M, double* c, double* s) {
+    r %= M;
+    if (r < 0) r += M;
+    if (M % 8 != 0) {
+        // M in {1, 2, 4}: the values are exactly 0 or +-1
+        const double k = (double)r / (double)M;
+        const double tc[4] = {1.0, 0.0, -1.0, 0.0}, ts[4] = {0.0, 1.0, 0.0, -1.0};
+        const int q = (int)(k * 4.0 + 0.5) & 3;
+        *c = tc[q];
+        *s = ts[q];
+        return;
+    }
+    const long q = (4 * r) / M;
+    const long e1 = r - q * (M / 4);
+    double cc, ss;
+    const double twopi = 6.283185307179586476925286766559;
+    if (2 * e1 <= M / 4) {
+        cc = cos(twopi * (double)e1 / (double)M);
+        ss = sin(twopi * (double)e1 / (double)M);
+    } else {
+        const long f = M / 4 - e1;
+        cc = sin(twopi * (double)f / (double)M);
+        ss = cos(twopi * (double)f / (double)M);
+    }
+    switch (q) {
+        case 0: *c = cc; *s = ss; break;
+        case 1: *c = -ss; *s = cc; break;
+        case 2: *c = -cc; *s = -ss; break;
+        default: *c = ss; *s = -cc; break;
+    }
+}
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) return FFTCG_EDEVICE; \
+    } while (0)
+
+static int check_device() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return FFTCG_EDEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FFTCG_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FFTCG_EDEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FFTCG_EDEVICE;
+    return FFTCG_OK;
+}
+
+// ---- workspaces -------------------------------------------------------------
+Workspace::~Workspace() { release(); }
+
+void Workspace::release() {
+    void* dev[] = {W, r, p, q, e, d32, part, st, slot, ls_pv, ls_pi, ls_out};
+    for (void* v : dev)
+        if (v) (void)hipFree(v);
+    if (h_slot) (void)hipHostFree(h_slot);
+    if (h_state) (void)hipHostFree(h_state);
+    if (h_status) (void)hipHostFree(h_status);
+    if (h_ls) (void)hipHostFree(h_ls);
+    for (int i = 0; i < 2; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    W = r = p = q = nullptr;
+    e = d32 = nullptr;
+    part = nullptr;
+    st = nullptr;
+    slot = nullptr;
+    h_slot = nullptr;
+    h_state = nullptr;
+    h_status = nullptr;
+    ls_pv = nullptr;
+    ls_pi = ls_out = nullptr;
+    h_ls = nullptr;
+    ev[0] = ev[1] = ev0 = ev1 = nullptr;
+}
+
+size_t workspace_bytes(int L, int M, int stride) {
+    const size_t n = (size_t)L * L;
+    const size_t N = (size_t)M / 2;
+    return N * L * 16 + 3 * n * 8 + 2 * n * 4 + (size_t)NPART_SETS * stride * 8 + sizeof(SolveState) +
+           sizeof(SlotDesc) + 4096;
+}
+
+int Workspace::init(int L_, int M_, int stride_) {
+    L = L_;
+    M = M_;
+    stride = stride_;
+    const size_t n = (size_t)L * L;
+    const size_t N = (size_t)M / 2;
+    HIPCHK(hipMalloc(&W, std::max<size_t>(N * L * 16, 256)));
+    HIPCHK(hipMalloc(&r, n * 8));
+    HIPCHK(hipMalloc(&p, n * 8));
+    HIPCHK(hipMalloc(&q, n * 8));
+    HIPCHK(hipMalloc((void**)&e, n * 4));
+    HIPCHK(hipMalloc((void**)&d32, n * 4));
+    HIPCHK(hipMalloc((void**)&part, (size_t)NPART_SETS * stride * 8));
+    HIPCHK(hipMalloc((void**)&st, sizeof(SolveState)));
+    HIPCHK(hipMalloc((void**)&slot, sizeof(SlotDesc)));
+    const int nb = loadstep_blocks((int)n);
+    HIPCHK(hipMalloc((void**)&ls_pv, nb * 8));
+    HIPCHK(hipMalloc((void**)&ls_pi, nb * 4));
+    HIPCHK(hipMalloc((void**)&ls_out, 16));
+    HIPCHK(hipHostMalloc((void**)&h_slot, sizeof(SlotDesc), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h_state, sizeof(SolveState), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h_status, 16, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void**)&d_status, h_status, 0));
+    HIPCHK(hipHostMalloc((void**)&h_ls, 16, hipHostMallocDefault));
+    HIPCHK(hipMemset(part, 0, (size_t)NPART_SETS * stride * 8));
+    for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    return FFTCG_OK;
+}
+
+}  // namespace fftcg
+
+using namespace fftcg;
+
+// ---- plan -------------------------------------------------------------------
+static int plan_stride(const EngineOps* ops, int L) {
+    int s = std::max(64, L);
+    if (ops) s = std::max({s, ops->rowblk32, ops->rowblk64, ops->g4});
+    return (s + 63) & ~63;
+}
+
+template <typename T>
+static std::vector<T> build_ghq(const double* g, int M, int TT) {
+    const int N = M / 2, MH = M / 2 + 1, NT = N / TT;
+    const double s = 1.0 / ((double)M * (double)M);
+    std::vector<T> out((size_t)NT * MH * TT);
+    for (int kt = 0; kt < NT; ++kt)
+        for (int m = 0; m < MH; ++m)
+            for (int kk = 0; kk < TT; ++kk)
+                out[((size_t)kt * MH + m) * TT + kk] = (T)(g[(size_t)m * M + kt * TT + kk] * s);
+    return out;
+}
+
+template <typename T>
+static std::vector<T> build_ghN(const double* g, int M) {
+    const int N = M / 2;
+    const double s = 1.0 / ((double)M * (double)M);
+    std::vector<T> out(N + 1);
+    for (int m = 0; m <= N; ++m) out[m] = (T)(g[(size_t)m * M + N] * s);
+    return out;
+}
+
+template <typename T>
+static int upload(void** dst, const std::vector<T>& v, size_t* bytes) {
+    const size_t b = std::max<size_t>(v.size() * sizeof(T), 16);
+    HIPCHK(hipMalloc(dst, b));
+    HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *bytes += b;
+    return FFTCG_OK;
+}
+
+fftcg_plan_s::~fftcg_plan_s() {
+    for (Workspace* w : all_ws) delete w;
+    void* dev[] = {tw32, tw64, ghq32, ghq64, ghN32, ghN64, apply_W};
+    for (void* v : dev)
+        if (v) (void)hipFree(v);
+    if (apply_ev) (void)hipEventDestroy(apply_ev);
+    fused_free(this);
+}
+
+int fftcg::plan_validate(int L, int padded, const double* g, double* gmin_out, double* gmax_out) {
+    if (!ispow2(L) || L < 2 || L > 2048) return FFTCG_EINVAL;
+    if (padded != 0 && padded != 1) return FFTCG_EINVAL;
+    if (!g) return FFTCG_EINVAL;
+    const int M = padded ? 2 * L : L;
+    double gmin = INFINITY, gmax = 0.0;
+    for (size_t i = 0; i < (size_t)M * M; ++i) {
+        if (!isfinite(g[i])) return FFTCG_EINVAL;
+        gmin = std::min(gmin, g[i]);
+        gmax = std::max(gmax, fabs(g[i]));
+    }
+    const double tolv = 1e-12 * gmax;
+    for (int m = 0; m < M; ++m)
+        for (int k = 0; k < M; ++k) {
+            const double v = g[(size_t)m * M + k];
+            if (fabs(v - g[(size_t)((M - m) % M) * M + k]) > tolv) return FFTCG_EINVAL;
+            if (fabs(v - g[(size_t)m * M + (M - k) % M]) > tolv) return FFTCG_EINVAL;
+        }
+    if (!(gmin > 0.0)) return FFTCG_ENOTSPD;
+    *gmin_out = gmin;
+    *gmax_out = gmax;
+    return FFTCG_OK;
+}
+
+extern "C" int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftcg_plan_t* out) {
+    if (!out) return FFTCG_EINVAL;
+    double gmin = 0, gmax = 0;
+    int rc = plan_validate(L, padded, kernel_spectrum, &gmin, &gmax);
+    if (rc != FFTCG_OK) return rc;
+    rc = check_device();
+    if (rc != FFTCG_OK) return rc;
+    const int M = padded ? 2 * L : L;
+    fftcg_plan_s* p = new (std::nothrow) fftcg_plan_s();
+    if (!p) return FFTCG_ENOMEM;
+    p->L = L;
+    p->M = M;
+    p->pad = padded;
+    p->gmin = gmin;
+    p->gmax = gmax;
+    (void)hipGetDevice(&p->device);
+    p->ops = find_engine(M, padded);
+    p->stride = plan_stride(p->ops, L);
+    // quarter spectrum (host copy, FP64) for the fused engine
+    p->quarter.resize((size_t)(M / 2 + 1) * (M / 2 + 1));
+    for (int m = 0; m <= M / 2; ++m)
+        for (int k = 0; k <= M / 2; ++k) p->quarter[(size_t)m * (M / 2 + 1) + k] = kernel_spectrum[(size_t)m * M + k];
+    // twiddles exp(-2 pi i m / M)
+    std::vector<double> tw64(2 * (size_t)M);
+    std::vector<float> tw32(2 * (size_t)M);
+    for (int m = 0; m < M; ++m) {
+        double c, s;
+        cos_sin_2pi(m, M, &c, &s);
+        tw64[2 * m] = c;
+        tw64[2 * m + 1] = -s;
+        tw32[2 * m] = (float)c;
+        tw32[2 * m + 1] = (float)-s;
+    }
+    size_t bytes = 0;
+    int r2 = FFTCG_OK;
+    if (p->ops) {
+        r2 = upload(&p->tw32, tw32, &bytes);
+        if (r2 == FFTCG_OK) r2 = upload(&p->tw64, tw64, &bytes);
+        if (r2 == FFTCG_OK) r2 = upload(&p->ghq32, build_ghq<float>(kernel_spectrum, M, p->ops->tt32), &bytes);
+        if (r2 == FFTCG_OK) r2 = upload(&p->ghq64, build_ghq<double>(kernel_spectrum, M, p->ops->tt64), &bytes);
+        if (r2 == FFTCG_OK) r2 = upload(&p->ghN32, build_ghN<float>(kernel_spectrum, M), &bytes);
+        if (r2 == FFTCG_OK) r2 = upload(&p->ghN64, build_ghN<double>(kernel_spectrum, M), &bytes);
+        if (r2 == FFTCG_OK && hipMalloc(&p->apply_W, std::max<size_t>((size_t)(M / 2) * L * 16, 256)) != hipSuccess)
+            r2 = FFTCG_ENOMEM;
+        bytes += (size_t)(M / 2) * L * 16;
+        if (r2 == FFTCG_OK && hipEventCreateWithFlags(&p->apply_ev, hipEventDisableTiming) != hipSuccess)
+            r2 = FFTCG_EDEVICE;
+    }
+    if (r2 == FFTCG_OK) r2 = fused_init(p, kernel_spectrum);
+    if (r2 != FFTCG_OK) {
+        delete p;
+        return r2 == FFTCG_EDEVICE ? FFTCG_EDEVICE : FFTCG_ENOMEM;
+    }
+    p->tabs = PlanTabs{p->tw32, p->ghq32, p->ghN32, p->tw64, p->ghq64, p->ghN64};
+    p->device_bytes = bytes + p->fused_bytes;
+    p->engine = FFTCG_ENGINE_AUTO;
+    *out = p;
+    return FFTCG_OK;
+}
+
+extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) {
+    if (!plan) return FFTCG_EINVAL;
+    if (plan->refs.load() > 0) return FFTCG_EINVAL;
+    (void)hipDeviceSynchronize();
+    delete plan;
+    return FFTCG_OK;
+}
+
+int fftcg::plan_engine(const fftcg_plan_s* p) {
+    if (p->engine == FFTCG_ENGINE_AUTO) return (p->M <= 128 && p->fused_ok) ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
+    return p->engine;
+}
+
+extern "C" int fftcg_plan_set_engine(fftcg_plan_t plan, int engine) {
+    if (!plan) return FFTCG_EINVAL;
+    if (engine == FFTCG_ENGINE_AUTO) {
+        plan->engine = engine;
+        return FFTCG_OK;
+    }
+    if (engine == FFTCG_ENGINE_MULTIPASS) {
+        if (!plan->ops) return FFTCG_EINVAL;
+        plan->engine = engine;
+        return FFTCG_OK;
+    }
+    if (engine == FFTCG_ENGINE_FUSED) {
+        if (!plan->fused_ok) return FFTCG_EINVAL;
+        plan->engine = engine;
+        return FFTCG_OK;
+    }
+    return FFTCG_EINVAL;
+}
+
+extern "C" int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* device_bytes) {
+    if (!plan) return FFTCG_EINVAL;
+    if (L) *L = plan->L;
+    if (M) *M = plan->M;
+    if (padded) *padded = plan->pad;
+    if (device_bytes) *device_bytes = plan->device_bytes;
+    return FFTCG_OK;
+}
+
+// ---- apply -------------------------------------------------------------------
+static bool overlap(const void* a, const void* b, size_t n) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + n && y < x + n;
+}
+
+extern "C" int fftcg_apply(fftcg_plan_t plan, int precision, const double* d, const double* x, double* y,
+                           void* stream) {
+    if (!plan || !d || !x || !y) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    const size_t nb = (size_t)plan->L * plan->L * 8;
+    if (overlap(y, x, nb) || overlap(y, d, nb)) return FFTCG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(plan->mu);
+    if (plan_engine(plan) == FFTCG_ENGINE_FUSED) {
+        return fused_apply(plan, precision, d, x, y, s);
+    }
+    if (!plan->ops) return FFTCG_EINVAL;
+    HIPCHK(hipStreamWaitEvent(s, plan->apply_ev, 0));
+    plan->ops->apply(precision, plan->tabs, d, x, y, plan->apply_W, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(plan->apply_ev, s));
+    return FFTCG_OK;
+}
+
+// ---- solve -------------------------------------------------------------------
+Workspace* fftcg::plan_acquire(fftcg_plan_s* p) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->free_ws.empty()) {
+        Workspace* w = p->free_ws.back();
+        p->free_ws.pop_back();
+        return w;
+    }
+    Workspace* w = new (std::nothrow) Workspace();
+    if (!w) return nullptr;
+    if (w->init(p->L, p->M, p->stride) != FFTCG_OK) {
+        delete w;
+        return nullptr;
+    }
+    p->all_ws.push_back(w);
+    return w;
+}
+
+void fftcg::plan_release(fftcg_plan_s* p, Workspace* w) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->free_ws.push_back(w);
+}
+
+void fftcg::init_state(SolveState* h, const fftcg_plan_s* p, int precision, double tol, int maxit, int refresh) {
+    memset(h, 0, sizeof(SolveState));
+    h->tol = tol;
+    h->tau = precision == FFTCG_MIXED ? 1e-8 : 1e-10;
+    h->gmin = p->gmin;
+    h->maxit = maxit;
+    h->refresh = precision == FFTCG_MIXED ? refresh : 0;
+    h->pause = 1;
+    h->restart = 1;
+    h->iters_literal = -1;
+    h->mixed = precision == FFTCG_MIXED ? 1 : 0;
+    h->trigger_rr = 0.0;
+    h->best_rt = INFINITY;
+}
+
+void fftcg::fill_slot(SlotDesc* h, const Workspace* w, double* x, const double* b, const double* d) {
+    memset(h, 0, sizeof(SlotDesc));
+    h->x = x;
+    h->b = b;
+    h->d = d;
+    h->r = w->r;
+    h->p = w->p;
+    h->q = w->q;
+    h->e = w->e;
+    h->d32 = w->d32;
+    h->W = w->W;
+    h->part = w->part;
+    h->st = w->st;
+    h->host_status = w->d_status;
+    h->active = 1;
+}
+
+int fftcg::chunk_iters_for(int L) { return L >= 512 ? 10 : 16; }
+
+int fftcg::solve_validate(fftcg_plan_t plan, int precision, const void* d, const void* b, double tol, int maxit,
+                   const void* x) {
+    if (!plan || !d || !b || !x) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    if (!(tol > 0.0) || !(tol < 1.0) || !isfinite(tol)) return FFTCG_EINVAL;
+    if (maxit < 1) return FFTCG_EINVAL;
+    return FFTCG_OK;
+}
+
+static void fill_info(fftcg_info* info, const SolveState& st, float ms) {
+    if (!info) return;
+    info->status = st.status;
+    info->iterations = st.iters;
+    info->iterations_literal = st.iters_literal;
+    info->checks = st.checks;
+    info->true_relres = st.true_relres;
+    info->error_bound = st.bound;
+    info->lambda_lb = st.lam_lb;
+    info->device_ms = ms;
+}
+
+static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, const double* b, const double* x0,
+                           double tol, int maxit, double* x, fftcg_info* info, hipStream_t s) {
+    Workspace* w = plan_acquire(plan);
+    if (!w) return FFTCG_ENOMEM;
+    const EngineOps* ops = plan->ops;
+    const size_t n = (size_t)plan->L * plan->L;
+    int rc = FFTCG_OK;
+    do {
+        fill_slot(w->h_slot, w, x, b, d);
+        init_state(w->h_state, plan, precision, tol, maxit, 50);
+        w->h_status[0] = 0;
+        w->h_status[1] = 0;
+        if (hipMemcpyAsync(w->slot, w->h_slot, sizeof(SlotDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(w->st, w->h_state, sizeof(SolveState), hipMemcpyHostToDevice, s) != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        if (hipEventRecord(w->ev0, s) != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        hipError_t he = hipSuccess;
+        if (!x0)
+            he = hipMemsetAsync(x, 0, n * 8, s);
+        else if (x0 != x)
+            he = hipMemcpyAsync(x, x0, n * 8, hipMemcpyDeviceToDevice, s);
+        if (he == hipSuccess && precision == FFTCG_MIXED) {
+            he = hipMemsetAsync(w->e, 0, n * 4, s);
+            if (he == hipSuccess) launch_to_f32(d, w->d32, (int)n, s);
+        }
+        if (he != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        ops->check(precision, plan->tabs, w->slot, 1, plan->stride, s);
+        const int K = chunk_iters_for(plan->L);
+        const long max_chunks = (long)maxit + 64;
+        long c = 0;
+        bool finished = false;
+        while (!finished) {
+            for (int k = 0; k < K; ++k) ops->iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
+            ops->check(precision, plan->tabs, w->slot, 1, plan->stride, s);
+            if (hipGetLastError() != hipSuccess || hipEventRecord(w->ev[c & 1], s) != hipSuccess) {
+                rc = FFTCG_EDEVICE;
+                break;
+            }
+            if (c >= 1) {
+                if (hipEventSynchronize(w->ev[(c - 1) & 1]) != hipSuccess) {
+                    rc = FFTCG_EDEVICE;
+                    break;
+                }
+                if (__atomic_load_n(&w->h_status[0], __ATOMIC_ACQUIRE)) finished = true;
+            }
+            ++c;
+            if (c > max_chunks) {
+                rc = FFTCG_EDEVICE;
+                break;
+            }
+        }
+        if (rc != FFTCG_OK) break;
+        if (hipEventRecord(w->ev1, s) != hipSuccess ||
+            hipMemcpyAsync(w->h_state, w->st, sizeof(SolveState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, w->ev0, w->ev1);
+        const SolveState st = *w->h_state;
+        if (st.bzero) {
+            if (hipMemsetAsync(x, 0, n * 8, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+                rc = FFTCG_EDEVICE;
+                break;
+            }
+        }
+        rc = st.status;
+        fill_info(info, st, ms);
+    } while (0);
+    plan_release(plan, w);
+    return rc;
+}
+
+extern "C" int fftcg_solve(fftcg_plan_t plan, int precision, const double* d, const double* b, const double* x0,
+                           double tol, int maxit, double* x, fftcg_info* info, void* stream) {
+    int rc = solve_validate(plan, precision, d, b, tol, maxit, x);
+    if (rc != FFTCG_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan_engine(plan) == FFTCG_ENGINE_FUSED) return fused_solve(plan, precision, d, b, x0, tol, maxit, x, info, s);
+    if (!plan->ops) return FFTCG_EINVAL;
+    return solve_multipass(plan, precision, d, b, x0, tol, maxit, x, info, s);
+}
+
+// ---- load step ---------------------------------------------------------------
+extern "C" int fftcg_loadstep(fftcg_plan_t plan, const double* x, const double* t, double* d, int* index,
+                              void* stream) {
+    if (!plan || !x || !t || !d || !index) return FFTCG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace* w = plan_acquire(plan);
+    if (!w) return FFTCG_ENOMEM;
+    const int n = plan->L * plan->L;
+    launch_loadstep(x, t, d, n, w->ls_pv, w->ls_pi, w->ls_out, s);
+    int rc = FFTCG_OK;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(w->h_ls, w->ls_out, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        rc = FFTCG_EDEVICE;
+    else
+        *index = w->h_ls[0];
+    plan_release(plan, w);
+    return rc;
+}
+
+// ---- misc -------------------------------------------------------------------
+extern "C" const char* fftcg_strerror(int status) {
+    switch (status) {
+        case FFTCG_OK: return "ok";
+        case FFTCG_PENDING: return "pending";
+        case FFTCG_EINVAL: return "invalid argument";
+        case FFTCG_ENOMEM: return "out of memory or over budget";
+        case FFTCG_ENOTSPD: return "spectrum not positive: operator not SPD";
+        case FFTCG_ENOCONV: return "not converged within maxit";
+        case FFTCG_EBREAKDOWN: return "CG breakdown (p.q <= 0 or non-finite)";
+        case FFTCG_EAGAIN: return "queue full, try again";
+        case FFTCG_EDEVICE: return "device error or no gfx950 GPU";
+        case FFTCG_ENOTFOUND: return "unknown ticket";
+        case FFTCG_ECANCELED: return "canceled";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char* fftcg_version(void) { return "fftcg 0.1.0 (gfx950)"; }

@@ -1,0 +1,86 @@
+// Host-side internals shared by the C ABI, the fused engine and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <mutex>
+#include <vector>
+
+#include "engine.hpp"
+#include "fftcg.h"
+#include "fftcg_types.hpp"
+
+namespace fftcg {
+
+// Device buffers of one in-flight solve (reused across solves of a plan).
+struct Workspace {
+    int L = 0, M = 0, stride = 0;
+    void* W = nullptr;  // pruned half spectrum, L x M/2 complex (FP64-sized)
+    void* r = nullptr;  // working vectors, L*L doubles each (FP32 uses half)
+    void* p = nullptr;
+    void* q = nullptr;
+    float* e = nullptr;    // FP32 correction (mixed mode)
+    float* d32 = nullptr;  // FP32 diagonal (mixed mode)
+    double* part = nullptr;
+    SolveState* st = nullptr;
+    SlotDesc* slot = nullptr;
+    SlotDesc* h_slot = nullptr;    // pinned staging
+    SolveState* h_state = nullptr; // pinned staging
+    int* h_status = nullptr;       // pinned, device-visible: {done, status}
+    int* d_status = nullptr;       // device view of h_status
+    double* ls_pv = nullptr;       // load-step partials
+    int* ls_pi = nullptr;
+    int* ls_out = nullptr;
+    int* h_ls = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int init(int L, int M, int stride);
+    void release();
+    ~Workspace();
+};
+
+size_t workspace_bytes(int L, int M, int stride);
+void cos_sin_2pi(long r, long M, double* c, double* s);
+int plan_validate(int L, int padded, const double* g, double* gmin, double* gmax);
+void init_state(SolveState* h, const struct ::fftcg_plan_s* p, int precision, double tol, int maxit, int refresh);
+void fill_slot(SlotDesc* h, const Workspace* w, double* x, const double* b, const double* d);
+int chunk_iters_for(int L);
+int solve_validate(fftcg_plan_t plan, int precision, const void* d, const void* b, double tol, int maxit,
+                   const void* x);
+
+}  // namespace fftcg
+
+struct fftcg_plan_s {
+    int L = 0, M = 0, pad = 0, device = 0;
+    int engine = FFTCG_ENGINE_AUTO;
+    int stride = 64;
+    double gmin = 0, gmax = 0;
+    const fftcg::EngineOps* ops = nullptr;
+    void* tw32 = nullptr;
+    void* tw64 = nullptr;
+    void* ghq32 = nullptr;
+    void* ghq64 = nullptr;
+    void* ghN32 = nullptr;
+    void* ghN64 = nullptr;
+    fftcg::PlanTabs tabs{};
+    std::vector<double> quarter;  // ghat(m, k), m, k in [0, M/2], FP64
+    size_t device_bytes = 0;
+    void* apply_W = nullptr;
+    hipEvent_t apply_ev = nullptr;
+    // fused (single-workgroup) engine tables
+    int fused_ok = 0;
+    void* f_tab64 = nullptr;  // per-plan constant tables of the fused engine
+    void* f_tab32 = nullptr;
+    size_t fused_bytes = 0;
+    std::mutex mu;
+    std::vector<fftcg::Workspace*> free_ws;
+    std::vector<fftcg::Workspace*> all_ws;
+    std::atomic<int> refs{0};
+    ~fftcg_plan_s();
+};
+
+namespace fftcg {
+int plan_engine(const fftcg_plan_s* p);
+Workspace* plan_acquire(fftcg_plan_s* p);
+void plan_release(fftcg_plan_s* p, Workspace* w);
+}  // namespace fftcg

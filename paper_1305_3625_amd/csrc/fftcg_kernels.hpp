@@ -1,0 +1,680 @@
+// Multi-pass engine: one operator product A v = d * v + C v in three HBM
+// passes over the pruned half spectrum W (L rows x M/2 packed columns).
+//
+//   row_fwd  (gather + forward R2C along rows)   v rows -> W
+//   col      (forward FFT, * ghat/M^2, inverse FFT along columns, in place)
+//   row_inv  (C2R along rows + crop + epilogue)   W -> q = d*v + Cv, partials
+//
+// Eq. (3) of the paper: C is diagonal in Fourier space, so one product is a
+// forward 2-D transform, a pointwise multiply by the static spectrum and an
+// inverse transform (Listing 4), the scaling of Listing 3 being folded into
+// the stored spectrum.  Listing 4 copies the real input into a complex buffer
+// and back; here the real input is packed two-per-complex (z[n] = v[2n] +
+// i v[2n+1]) so the row transforms have length M/2 and the column pass
+// touches only the M/2 non-redundant column frequencies.  The Nyquist column
+// k = M/2 is real for every row, as is k = 0, so both ride in packed column 0
+// (real part k = 0, imaginary part k = M/2).
+//
+// On the zero-padded grid (M = 2L) rows >= L and inputs >= L are zero, so the
+// row pass transforms only L rows and the first radix-16 stage of every
+// forward transform sees only its lower 8 inputs; outputs >= L are cropped,
+// so the last inverse stage stores only its lower 8 outputs.
+//
+// W layout: tiles of TT columns, W[((kt * L) + i) * TT + kk] for column
+// k = kt * TT + kk, so a column tile is one contiguous block and each row
+// writes runs of RPW * TT complex values.
+#pragma once
+#include <type_traits>
+#include "fftcg_dev.hpp"
+#include "fftcg_types.hpp"
+
+namespace fftcg {
+
+#ifndef FFTCG_STATUS_CODES
+#define FFTCG_STATUS_CODES
+enum { ST_OK = 0, ST_EINVAL = -1, ST_ENOCONV = -4, ST_EBREAKDOWN = -5 };
+#endif
+
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <typename T, int M, int PAD>
+struct Geo {
+    static constexpr int L = PAD ? M / 2 : M;
+    static constexpr int N = M / 2;  // complex row length = number of packed columns
+    // row passes
+    static constexpr int ER = fft_elems(N);
+    static constexpr int PR = N / ER;
+    static constexpr int ROW_WORDS = LdsLay<T, 1, 4, 1>::words(N);
+    static constexpr int ROW_LDS_CAP = 65536 / (int)sizeof(cx<T>);
+    static constexpr int RPW0 = cmin(L, cmax(1, 256 / PR));
+    static constexpr int RPW_fit(int r) { return (r > 1 && r * ROW_WORDS > ROW_LDS_CAP) ? RPW_fit(r / 2) : r; }
+    static constexpr int RPW = RPW_fit(RPW0);
+    static constexpr int ROW_THREADS = RPW * PR;
+    static constexpr int ROW_BLOCKS = L / RPW;
+    // column pass
+    static constexpr int EC = fft_elems(M);
+    static constexpr int PC = M / EC;
+    static constexpr int COL_LDS_CAP = 73728 / (int)sizeof(cx<T>);
+    static constexpr int TT_fit(int t) {
+        return (t > 1 && (t * M + (t * M) / 16 + t > COL_LDS_CAP || t * PC > 1024)) ? TT_fit(t / 2) : t;
+    }
+    static constexpr int TT = TT_fit(cmin(N, 4));
+    static constexpr int COL_SH = ilog2c(16 * TT);
+    static constexpr int COL_THREADS = TT * PC;
+    static constexpr int NTILE = N / TT;
+    static constexpr int MH = M / 2 + 1;
+};
+
+// ---- slot access policies -------------------------------------------------
+struct ByPtr {
+    const SlotDesc* p;
+    __device__ __forceinline__ const SlotDesc& get() const { return p[blockIdx.y]; }
+};
+struct ByVal {
+    SlotDesc s;
+    __device__ __forceinline__ const SlotDesc& get() const { return s; }
+};
+
+// gates: which slots a kernel works on
+struct GateAlways {
+    static __device__ __forceinline__ bool ok(const SlotDesc&) { return true; }
+};
+struct GateIter {  // CG iteration kernels
+    static __device__ __forceinline__ bool ok(const SlotDesc& sd) {
+        return sd.active && !sd.st->done && !sd.st->pause;
+    }
+};
+struct GateCheck {  // FP64 check kernels
+    static __device__ __forceinline__ bool ok(const SlotDesc& sd) {
+        return sd.active && !sd.st->done && sd.st->pause;
+    }
+};
+
+template <typename T>
+struct Tab {
+    const cx<T>* tw;   // exp(-2 pi i m / M), m in [0, M)
+    const T* ghq;      // quarter spectrum / M^2 in tile layout
+    const T* ghN;      // ghat(m, M/2) / M^2, m in [0, M/2]
+};
+
+template <typename T, int N>
+struct PairT;
+template <>
+struct PairT<float, 2> { using type = float2; };
+template <>
+struct PairT<double, 2> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ cx<T> ld2(const T* p) {
+    using V = typename PairT<T, 2>::type;
+    V v = *reinterpret_cast<const V*>(p);
+    return mkc(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T* p, cx<T> c) {
+    using V = typename PairT<T, 2>::type;
+    V v;
+    v.x = c.x;
+    v.y = c.y;
+    *reinterpret_cast<V*>(p) = v;
+}
+__device__ __forceinline__ cx<double> ld2f(const float* p) {
+    float2 v = *reinterpret_cast<const float2*>(p);
+    return mkc((double)v.x, (double)v.y);
+}
+
+// ==== prologues of the row-forward pass ====================================
+
+// fftcg_apply: transform x (FP64 in memory), rounded to T.
+template <typename T>
+struct ProApply {
+    static constexpr int L_ = 0;
+    struct Sh {};
+    using Gate = GateAlways;
+    static __device__ __forceinline__ bool begin(const SlotDesc&, Sh&, int, int) { return true; }
+    template <int L>
+    static __device__ __forceinline__ cx<T> load2(const SlotDesc& sd, const Sh&, int row, int col) {
+        cx<double> v = ld2<double>(sd.x + (size_t)row * L + col);
+        return mkc((T)v.x, (T)v.y);
+    }
+};
+
+// CG iteration: x_acc += alpha p_old (pending update of the last iteration),
+// p = r + beta p_old (or p = r on restart), then transform p.
+// W: working precision of r, p; XA: accumulator (double: x itself; float: e).
+template <typename W, typename XA, int NT>
+struct ProCG {
+    struct Sh {
+        double red[(NT + 63) / 64];
+        W alpha, beta;
+        int restart;
+    };
+    using Gate = GateIter;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd, Sh& sh, int npart_rr, int stride) {
+        if (!GateIter::ok(sd)) return false;
+        SolveState* st = sd.st;
+        const double rr = sum_partials<NT>(sd.part + PS_RR * stride, npart_rr, sh.red);
+        const int iters = st->iters;
+        // a check is due at maxit, every `refresh` iterations (mixed mode), or
+        // when the recursive residual meets the stop rule; the last needs at
+        // least one iteration since the previous check so checks always
+        // alternate with progress
+        const bool progressed = iters > st->last_check_iter;
+        const bool periodic = st->refresh > 0 && iters - st->last_check_iter >= st->refresh;
+        const bool candidate = progressed && !(rr > st->trigger_rr);
+        const bool pause = iters >= st->maxit || candidate || periodic;
+        if (pause) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) st->pause = 1;
+            return false;
+        }
+        const int restart = st->restart;
+        const double beta = restart ? 0.0 : rr / st->rho_prev;
+        sh.alpha = (W)st->alpha;
+        sh.beta = (W)beta;
+        sh.restart = restart;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->rho_cur = rr;
+        return true;
+    }
+    template <int L>
+    static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col) {
+        const size_t idx = (size_t)row * L + col;
+        W* p = reinterpret_cast<W*>(sd.p);
+        const W* r = reinterpret_cast<const W*>(sd.r);
+        cx<W> r2 = ld2<W>(r + idx);
+        cx<W> p2;
+        if (sh.restart) {
+            p2 = r2;
+        } else {
+            cx<W> po = ld2<W>(p + idx);
+            p2 = mkc(r2.x + sh.beta * po.x, r2.y + sh.beta * po.y);
+            if (sh.alpha != W(0)) {
+                XA* xa = reinterpret_cast<XA*>(sizeof(XA) == 8 ? (void*)sd.x : (void*)sd.e);
+                cx<XA> xv = ld2<XA>(xa + idx);
+                xv.x += (XA)sh.alpha * (XA)po.x;
+                xv.y += (XA)sh.alpha * (XA)po.y;
+                st2<XA>(xa + idx, xv);
+            }
+        }
+        st2<W>(p + idx, p2);
+        return p2;
+    }
+};
+
+// FP64 check: x <- x + e + alpha p (flush of the pending updates), e <- 0,
+// transform x in FP64.
+template <typename W, int NT>
+struct ProCheck {
+    struct Sh {
+        double alpha;
+        int mixed;
+    };
+    using Gate = GateCheck;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd, Sh& sh, int, int) {
+        if (!GateCheck::ok(sd)) return false;
+        sh.alpha = sd.st->alpha;
+        sh.mixed = sd.st->mixed;
+        return true;
+    }
+    template <int L>
+    static __device__ __forceinline__ cx<double> load2(const SlotDesc& sd, const Sh& sh, int row, int col) {
+        const size_t idx = (size_t)row * L + col;
+        cx<double> xv = ld2<double>(sd.x + idx);
+        if (sh.mixed) {
+            cx<double> ev = ld2f(sd.e + idx);
+            xv.x += ev.x;
+            xv.y += ev.y;
+            st2<float>(sd.e + idx, mkc(0.0f, 0.0f));
+        }
+        if (sh.alpha != 0.0) {
+            const W* p = reinterpret_cast<const W*>(sd.p);
+            cx<W> pv = ld2<W>(p + idx);
+            xv.x += sh.alpha * (double)pv.x;
+            xv.y += sh.alpha * (double)pv.y;
+        }
+        st2<double>(sd.x + idx, xv);
+        return xv;
+    }
+};
+
+// ==== epilogues of the row-inverse pass ====================================
+
+// fftcg_apply: y = d * x (FP64) + C x.
+template <typename T>
+struct EpiApply {
+    static constexpr int NACC = 0;
+    using Gate = GateAlways;
+    static __device__ __forceinline__ bool begin(const SlotDesc&) { return true; }
+    template <int L>
+    static __device__ __forceinline__ void out2(const SlotDesc& sd, int row, int col, T c0, T c1, double*) {
+        const size_t idx = (size_t)row * L + col;
+        cx<double> dv = ld2<double>(sd.d + idx);
+        cx<double> xv = ld2<double>(sd.x + idx);
+        st2<double>(sd.y + idx, mkc(dv.x * xv.x + (double)c0, dv.y * xv.y + (double)c1));
+    }
+    static __device__ __forceinline__ void finish(const SlotDesc&, const double*, int) {}
+};
+
+// CG iteration: q = d p + C p; partial p . q (FP64 accumulation).
+template <typename W>
+struct EpiCG {
+    static constexpr int NACC = 1;
+    using Gate = GateIter;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return GateIter::ok(sd); }
+    template <int L>
+    static __device__ __forceinline__ void out2(const SlotDesc& sd, int row, int col, W c0, W c1, double* acc) {
+        const size_t idx = (size_t)row * L + col;
+        const W* p = reinterpret_cast<const W*>(sd.p);
+        W* q = reinterpret_cast<W*>(sd.q);
+        cx<W> pv = ld2<W>(p + idx);
+        cx<W> dv;
+        if constexpr (sizeof(W) == 4) {
+            dv = ld2<float>(sd.d32 + idx);
+        } else {
+            dv = ld2<double>(sd.d + idx);
+        }
+        cx<W> qv = mkc(dv.x * pv.x + c0, dv.y * pv.y + c1);
+        st2<W>(q + idx, qv);
+        acc[0] += (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
+    }
+};
+
+// FP64 check: r64 = b - d x - C x; r (working precision) <- r64; partials of
+// |r64|^2, |x|^2, |b|^2, |r|^2, min d and the count of invalid inputs.
+template <typename W>
+struct EpiCheck {
+    static constexpr int NACC = 6;
+    using Gate = GateCheck;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return GateCheck::ok(sd); }
+    template <int L>
+    static __device__ __forceinline__ void out2(const SlotDesc& sd, int row, int col, double c0, double c1,
+                                                double* acc) {
+        const size_t idx = (size_t)row * L + col;
+        cx<double> xv = ld2<double>(sd.x + idx);
+        cx<double> bv = ld2<double>(sd.b + idx);
+        cx<double> dv = ld2<double>(sd.d + idx);
+        const double r0 = bv.x - (dv.x * xv.x + c0);
+        const double r1 = bv.y - (dv.y * xv.y + c1);
+        const W w0 = (W)r0, w1 = (W)r1;
+        st2<W>(reinterpret_cast<W*>(sd.r) + idx, mkc(w0, w1));
+        acc[0] += r0 * r0 + r1 * r1;
+        acc[1] += xv.x * xv.x + xv.y * xv.y;
+        acc[2] += bv.x * bv.x + bv.y * bv.y;
+        acc[3] += (double)w0 * (double)w0 + (double)w1 * (double)w1;
+        acc[4] = fmin(acc[4], fmin(dv.x, dv.y));
+        const bool ok = isfinite(bv.x) && isfinite(bv.y) && isfinite(dv.x) && isfinite(dv.y) &&
+                        dv.x >= 0.0 && dv.y >= 0.0;
+        acc[5] += ok ? 0.0 : 1.0;
+    }
+};
+
+// ==== kernels ==============================================================
+
+template <typename T, int M, int PAD, class Pro, class Slot, int NT>
+__global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart_rr, int stride) {
+    using G = Geo<T, M, PAD>;
+    constexpr int N = G::N, E = G::ER, P = G::PR, RPW = G::RPW, L = G::L, TT = G::TT;
+    constexpr int WORDS = G::ROW_WORDS;
+    static_assert(NT == G::ROW_THREADS, "row-forward block size");
+    __shared__ cx<T> lds[RPW * WORDS];
+    __shared__ typename Pro::Sh sh;
+    const SlotDesc& sd = slot.get();
+    if (!Pro::begin(sd, sh, npart_rr, stride)) return;
+    const int tid = threadIdx.x;
+    const int rl = tid / P, j = tid % P;
+    const int row = blockIdx.x * RPW + rl;
+    LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
+    cx<T> v[E];
+    constexpr int NSTG = fft_nstages(N);
+    constexpr int R1 = NSTG > 0 ? fft_radix(N, false, 0) : 1;
+#pragma unroll
+    for (int u = 0; u < E / R1; ++u) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            if (PAD && r >= R1 / 2) continue;  // known zeros (padded grid)
+            const int n = (j + u * P) + r * (N / R1);
+            v[u * R1 + r] = Pro::template load2<L>(sd, sh, row, 2 * n);
+        }
+    }
+    fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
+    constexpr int RL = NSTG > 0 ? fft_radix(N, false, NSTG - 1) : 1;
+#pragma unroll
+    for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) lay.st((j + u * P) + r * (N / RL), v[u * RL + r]);
+    __syncthreads();
+    cx<T>* Wb = reinterpret_cast<cx<T>*>(sd.W);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int qi = tid + s * NT;
+        const int kk = qi % TT;
+        const int il = (qi / TT) % RPW;
+        const int kt = qi / (TT * RPW);
+        const int k = kt * TT + kk;
+        LdsLay<T, 1, 4, 1> rl2{lds + il * WORDS, 0};
+        const cx<T> Zk = rl2.ld(k);
+        cx<T> out;
+        if (k == 0) {
+            out = mkc(Zk.x + Zk.y, Zk.x - Zk.y);
+        } else {
+            const cx<T> B = conjc(rl2.ld(N - k));
+            const cx<T> s1 = Zk + B, d1 = Zk - B;
+            const cx<T> wd = cmul(tab.tw[k], d1);
+            out = mkc(T(0.5) * (s1.x + wd.y), T(0.5) * (s1.y - wd.x));
+        }
+        Wb[((size_t)kt * L + blockIdx.x * RPW + il) * TT + kk] = out;
+    }
+}
+
+template <typename T, int M, int PAD, class Gate, class Slot, int NT>
+__global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
+    using G = Geo<T, M, PAD>;
+    constexpr int E = G::EC, P = G::PC, TT = G::TT, L = G::L, MH = G::MH;
+    static_assert(NT == G::COL_THREADS, "column block size");
+    using Lay = LdsLay<T, TT, G::COL_SH, TT>;
+    __shared__ cx<T> lds[Lay::words(M)];
+    const SlotDesc& sd = slot.get();
+    if (!Gate::ok(sd)) return;
+    const int kt = blockIdx.x;
+    const int tid = threadIdx.x, kk = tid % TT, j = tid / TT;
+    Lay lay{lds, kk};
+    cx<T>* Wt = reinterpret_cast<cx<T>*>(sd.W) + (size_t)kt * L * TT;
+    cx<T> v[E];
+    constexpr int NSTG = fft_nstages(M);
+    constexpr int R1 = fft_radix(M, false, 0);
+#pragma unroll
+    for (int u = 0; u < E / R1; ++u)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            if (PAD && r >= R1 / 2) continue;
+            const int n = (j + u * P) + r * (M / R1);
+            v[u * R1 + r] = Wt[(size_t)n * TT + kk];
+        }
+    fft_run<T, M, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
+    constexpr int RL = fft_radix(M, false, NSTG - 1);
+    const T* g = tab.ghq + (size_t)kt * MH * TT;
+    if (kt == 0) {
+        // packed column 0 carries k = 0 (real part) and k = M/2 (imaginary
+        // part): result(m) = s(m) W(m) + t(m) conj(W(M - m)),
+        // s = (g0 + gN)/2, t = (g0 - gN)/2.
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) lay.st((j + u * P) + r * (M / RL), v[u * RL + r]);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int m = (j + u * P) + r * (M / RL);
+                const int mp = m <= M - m ? m : M - m;
+                const cx<T> a = v[u * RL + r];
+                if (kk == 0) {
+                    const cx<T> bm = conjc(lay.ld((M - m) & (M - 1)));
+                    const T g0 = g[mp * TT], gN = tab.ghN[mp];
+                    const T s = T(0.5) * (g0 + gN), t = T(0.5) * (g0 - gN);
+                    v[u * RL + r] = mkc(s * a.x + t * bm.x, s * a.y + t * bm.y);
+                } else {
+                    v[u * RL + r] = scalec(a, g[mp * TT + kk]);
+                }
+            }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int m = (j + u * P) + r * (M / RL);
+                const int mp = m <= M - m ? m : M - m;
+                v[u * RL + r] = scalec(v[u * RL + r], g[mp * TT + kk]);
+            }
+    }
+    fft_run<T, M, M, +1, true, false>(v, lay, j, tab.tw);
+    constexpr int RZ = fft_radix(M, true, NSTG - 1);
+#pragma unroll
+    for (int u = 0; u < E / RZ; ++u)
+#pragma unroll
+        for (int r = 0; r < RZ; ++r) {
+            if (PAD && r >= RZ / 2) continue;
+            const int n = (j + u * P) + r * (M / RZ);
+            Wt[(size_t)n * TT + kk] = v[u * RZ + r];
+        }
+}
+
+template <typename T, int M, int PAD, class Epi, class Slot, int NT>
+__global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int stride) {
+    using G = Geo<T, M, PAD>;
+    constexpr int N = G::N, E = G::ER, P = G::PR, RPW = G::RPW, L = G::L, TT = G::TT;
+    constexpr int WORDS = G::ROW_WORDS;
+    static_assert(NT == G::ROW_THREADS, "row-inverse block size");
+    __shared__ cx<T> lds[RPW * WORDS];
+    __shared__ double red[(NT + 63) / 64];
+    const SlotDesc& sd = slot.get();
+    if (!Epi::begin(sd)) return;
+    const int tid = threadIdx.x;
+    const int rl = tid / P, j = tid % P;
+    const int row0 = blockIdx.x * RPW;
+    const cx<T>* Wb = reinterpret_cast<const cx<T>*>(sd.W);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int qi = tid + s * NT;
+        const int kk = qi % TT;
+        const int il = (qi / TT) % RPW;
+        const int kt = qi / (TT * RPW);
+        LdsLay<T, 1, 4, 1> l2{lds + il * WORDS, 0};
+        l2.st(kt * TT + kk, Wb[((size_t)kt * L + row0 + il) * TT + kk]);
+    }
+    __syncthreads();
+    LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
+    cx<T> v[E];
+    constexpr int NSTG = fft_nstages(N);
+    constexpr int R1 = NSTG > 0 ? fft_radix(N, true, 0) : 1;
+#pragma unroll
+    for (int u = 0; u < E / R1; ++u)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int k = (j + u * P) + r * (N / R1);
+            const cx<T> Y = lay.ld(k);
+            cx<T> Z;
+            if (k == 0) {
+                Z = mkc(Y.x + Y.y, Y.x - Y.y);
+            } else {
+                const cx<T> B = conjc(lay.ld(N - k));
+                const cx<T> s1 = Y + B, d1 = Y - B;
+                const cx<T> wd = cmul(conjc(tab.tw[k]), d1);
+                Z = mkc(s1.x - wd.y, s1.y + wd.x);
+            }
+            v[u * R1 + r] = Z;
+        }
+    __syncthreads();
+    fft_run<T, N, M, +1, true, false>(v, lay, j, tab.tw);
+    constexpr int RL = NSTG > 0 ? fft_radix(N, true, NSTG - 1) : 1;
+    double acc[Epi::NACC > 0 ? Epi::NACC : 1];
+#pragma unroll
+    for (int a = 0; a < (Epi::NACC > 0 ? Epi::NACC : 1); ++a) acc[a] = 0.0;
+    if constexpr (Epi::NACC > 4) acc[4] = 1.0e300;
+    const int row = row0 + rl;
+#pragma unroll
+    for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            if (PAD && RL > 1 && r >= RL / 2) continue;
+            const int n = (j + u * P) + r * (N / RL);
+            Epi::template out2<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, acc);
+        }
+    if constexpr (Epi::NACC > 0) {
+        double* part = sd.part;
+        if constexpr (Epi::NACC == 1) {
+            const double s = block_sum<NT>(acc[0], red);
+            if (tid == 0) part[PS_PQ * stride + blockIdx.x] = s;
+        } else {
+            const int sets[6] = {PS_CHK_R, PS_CHK_X, PS_CHK_B, PS_CHK_RW, PS_CHK_DMIN, PS_CHK_BAD};
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const double s = (a == 4) ? block_min<NT>(acc[a], red) : block_sum<NT>(acc[a], red);
+                if (tid == 0) part[sets[a] * stride + blockIdx.x] = s;
+            }
+        }
+    }
+}
+
+// r <- r - alpha q, partial r . r.  alpha = rho / (p . q) from the partials
+// of the row-inverse pass (all blocks reduce them in the same order).
+template <typename W, int NT>
+__global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, int stride) {
+    __shared__ double red[(NT + 63) / 64];
+    const SlotDesc& sd = slot.get();
+    if (!GateIter::ok(sd)) return;
+    SolveState* st = sd.st;
+    const double pq = sum_partials<NT>(sd.part + PS_PQ * stride, npart_pq, red);
+    const double rho = st->rho_cur;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->status = ST_EBREAKDOWN;
+            st->done = 1;
+            if (sd.host_status) {
+                __hip_atomic_store(sd.host_status + 1, ST_EBREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(sd.host_status, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->alpha = alpha;
+        st->rho_prev = rho;
+        st->iters += 1;
+        st->restart = 0;
+    }
+    constexpr int VW = sizeof(W) == 4 ? 4 : 2;
+    using V = typename std::conditional<sizeof(W) == 4, float4, double2>::type;
+    const int nv = n / VW;
+    const int per = (nv + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * per;
+    const int hi = lo + per < nv ? lo + per : nv;
+    V* r = reinterpret_cast<V*>(sd.r);
+    const V* q = reinterpret_cast<const V*>(sd.q);
+    const W a = (W)alpha;
+    double acc = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += NT) {
+        V rv = r[i];
+        const V qv = q[i];
+        if constexpr (VW == 4) {
+            rv.x -= a * qv.x;
+            rv.y -= a * qv.y;
+            rv.z -= a * qv.z;
+            rv.w -= a * qv.w;
+            acc += (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z + (double)rv.w * rv.w;
+        } else {
+            rv.x -= a * qv.x;
+            rv.y -= a * qv.y;
+            acc += rv.x * rv.x + rv.y * rv.y;
+        }
+        r[i] = rv;
+    }
+    const double s = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) sd.part[PS_RR * stride + blockIdx.x] = s;
+}
+
+// Single-block finaliser of an FP64 check: stop decision, residual
+// replacement, restart guard, and status for the host.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, int npart_rr, int stride) {
+    __shared__ double red[(NT + 63) / 64];
+    __shared__ int s_update;
+    const SlotDesc& sd = slot.get();
+    if (!sd.active) return;
+    SolveState* st = sd.st;
+    if (st->done || !st->pause) {
+        if (threadIdx.x == 0 && sd.host_status) {
+            __hip_atomic_store(sd.host_status + 1, st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(sd.host_status, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        return;
+    }
+    const double* part = sd.part;
+    const double R = sum_partials<NT>(part + PS_CHK_R * stride, npart_chk, red);
+    const double X = sum_partials<NT>(part + PS_CHK_X * stride, npart_chk, red);
+    const double B = sum_partials<NT>(part + PS_CHK_B * stride, npart_chk, red);
+    const double RW = sum_partials<NT>(part + PS_CHK_RW * stride, npart_chk, red);
+    const double BAD = sum_partials<NT>(part + PS_CHK_BAD * stride, npart_chk, red);
+    double dmin = 1.0e300;
+    for (int i = threadIdx.x; i < npart_chk; i += NT) dmin = fmin(dmin, part[PS_CHK_DMIN * stride + i]);
+    dmin = block_min<NT>(dmin, red);
+    if (threadIdx.x == 0) {
+        int update = 0;
+        const bool first = st->checks == 0;
+        st->checks += 1;
+        if (first) {
+            st->bnorm = sqrt(B);
+            st->lam_lb = dmin + st->gmin;
+        }
+        const double rt = sqrt(R), xn = sqrt(X), bn = st->bnorm;
+        if (first && BAD > 0.0) {
+            st->status = ST_EINVAL;
+            st->done = 1;
+        } else if (first && bn == 0.0) {
+            st->status = ST_OK;
+            st->done = 1;
+            st->bzero = 1;
+            st->true_relres = 0.0;
+            st->bound = 0.0;
+        } else if (!isfinite(rt) || !isfinite(xn)) {
+            st->status = ST_EBREAKDOWN;
+            st->done = 1;
+        } else {
+            const double tau = st->tau, lam = st->lam_lb;
+            const bool lit = rt <= st->tol * bn;
+            const double cert_target = tau * lam * xn / (1.0 + tau);
+            const bool cert = rt <= cert_target;
+            const double e = rt / lam;
+            st->true_relres = rt / bn;
+            st->bound = xn > e ? e / (xn - e) : 1.0e300;
+            if (lit && st->iters_literal < 0) st->iters_literal = st->iters;
+            if (lit && cert) {
+                st->status = ST_OK;
+                st->done = 1;
+            } else if (st->iters >= st->maxit) {
+                st->status = ST_ENOCONV;
+                st->done = 1;
+            } else {
+                double trig = st->tol * bn;
+                if (xn > 0.0 && cert_target < trig) trig = cert_target;
+                st->trigger_rr = trig * trig;
+                if (first) {
+                    st->worse = 0;
+                    st->best_rt = rt;
+                } else if (rt >= st->best_rt) {
+                    st->worse += 1;
+                } else {
+                    st->worse = 0;
+                    st->best_rt = rt;
+                }
+                if (st->worse >= 2) {
+                    st->restart = 1;
+                    st->worse = 0;
+                }
+                st->alpha = 0.0;
+                st->last_check_iter = st->iters;
+                st->last_rt = rt;
+                st->xnorm = xn;
+                st->pause = 0;
+                update = 1;
+            }
+        }
+        s_update = update;
+        if (sd.host_status) {
+            __hip_atomic_store(sd.host_status + 1, st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(sd.host_status, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    __syncthreads();
+    if (s_update) {
+        // residual replacement: the next iteration's rho is |r|^2 of the new r
+        double* prr = sd.part + PS_RR * stride;
+        for (int i = threadIdx.x; i < npart_rr; i += NT) prr[i] = (i == 0) ? RW : 0.0;
+    }
+}
+
+
+}  // namespace fftcg

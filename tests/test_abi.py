@@ -1,0 +1,98 @@
+"""The C ABI on the CPU: the library loads, exports every symbol the header
+declares, and rejects invalid arguments before touching a device."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1305_3625_amd import binding
+from workloads import spectrum
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fftcg.h")
+
+
+def header_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fftcg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_matches_binding_list():
+    assert header_symbols() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_symbol(lib):
+    for name in header_symbols():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (fftcg_\w+)", out))
+    assert set(header_symbols()) <= exported
+
+
+def test_strerror_and_version(lib):
+    assert binding.strerror(0) == "ok"
+    assert "invalid" in binding.strerror(-1)
+    assert binding.strerror(12345) == "unknown status"
+    assert lib.fftcg_version().decode().startswith("fftcg")
+
+
+def _plan(lib, L, padded, g):
+    h = ctypes.c_void_p()
+    gp = None if g is None else np.ascontiguousarray(g).ctypes.data_as(ctypes.c_void_p)
+    return lib.fftcg_plan(L, padded, gp, ctypes.byref(h))
+
+
+@pytest.mark.parametrize("L,padded", [(0, 0), (3, 0), (6, 1), (4096, 0), (1, 0), (8, 2), (8, -1)])
+def test_plan_rejects_bad_sizes(lib, L, padded):
+    M = max(2, 2 * L if padded == 1 else max(L, 1))
+    g = np.ones((M, M))
+    assert _plan(lib, L, padded, g) == binding.EINVAL
+
+
+def test_plan_rejects_null(lib):
+    assert _plan(lib, 8, 0, None) == binding.EINVAL
+    g = spectrum(8, 1e-2)
+    assert lib.fftcg_plan(8, 0, g.ctypes.data_as(ctypes.c_void_p), None) == binding.EINVAL
+
+
+def test_plan_rejects_non_even_and_non_finite(lib):
+    g = spectrum(16, 1e-2).copy()
+    g[1, 2] *= 1.01          # breaks evenness in m (g[15, 2] unchanged)
+    assert _plan(lib, 16, 0, g) == binding.EINVAL
+    g = spectrum(16, 1e-2).copy()
+    g[3, 3] = np.nan
+    assert _plan(lib, 16, 0, g) == binding.EINVAL
+    g = spectrum(32, 1e-2).copy()
+    g[0, 0] = np.inf
+    assert _plan(lib, 16, 1, g) == binding.EINVAL
+
+
+def test_plan_rejects_non_positive(lib):
+    g = spectrum(16, 1e-2) - 1.0     # even, finite, has negative entries
+    assert _plan(lib, 16, 0, g) == binding.ENOTSPD
+    g = np.zeros((16, 16))
+    assert _plan(lib, 16, 0, g) == binding.ENOTSPD
+
+
+def test_valid_plan_without_gpu_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    assert _plan(lib, 8, 0, spectrum(8, 1e-2)) == binding.EDEVICE
+
+
+def test_null_plan_calls(lib):
+    P = ctypes.c_void_p
+    info = binding.Info()
+    assert lib.fftcg_apply(None, 0, P(1), P(2), P(3), None) == binding.EINVAL
+    assert lib.fftcg_solve(None, 0, P(1), P(2), None, 1e-8, 10, P(3), ctypes.byref(info), None) == binding.EINVAL
+    assert lib.fftcg_plan_destroy(None) == binding.EINVAL
+    assert lib.fftcg_plan_set_engine(None, 0) == binding.EINVAL
+    assert lib.fftcg_plan_info(None, None, None, None, None) == binding.EINVAL
+    idx = ctypes.c_int()
+    assert lib.fftcg_loadstep(None, P(1), P(2), P(3), ctypes.byref(idx), None) == binding.EINVAL

@@ -1,0 +1,132 @@
+"""Parity of one operator product y = (diag(d) + C) x on the GPU against the
+oracle: the direct real-space sum on small and medium grids, numpy's FFT
+route (pinned against the direct sum) on large grids, single sampled outputs
+at the largest grid, plane-wave eigenpairs, and a canary past the output."""
+
+import numpy as np
+import pytest
+
+from paper_1305_3625_amd import binding
+from workloads import spectrum
+from oracle import kernel_table, apply_direct, apply_fft, apply_direct_at
+from gpu_util import dev, host, relerr, banner
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(L, p) for L in (2, 4, 8, 16, 32, 64, 128) for p in (0, 1)]
+
+
+def _inputs(L, padded, seed):
+    rng = np.random.default_rng([11, L, padded, seed])
+    d = rng.uniform(0.0, 1.5, (L, L))
+    d[rng.random((L, L)) < 0.3] = 0.0
+    x = rng.standard_normal((L, L))
+    return d, x
+
+
+@pytest.mark.parametrize("L,padded", SMALL)
+@pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS])
+def test_apply_small_direct(L, padded, engine):
+    M = 2 * L if padded else L
+    eps = 1e-3
+    gh = spectrum(M, eps)
+    g = kernel_table(gh)
+    plan = binding.Plan(L, padded, gh)
+    plan.set_engine(engine)
+    d, x = _inputs(L, padded, 0)
+    ref = apply_direct(g, d, x, padded)
+    banner("apply", L, padded, engine)
+    for prec, tol in ((binding.FP64, 1e-13), (binding.MIXED, 2e-6)):
+        y = dev(np.zeros((L, L)))
+        plan.apply(dev(d), dev(x), y, precision=prec)
+        err = relerr(host(y), ref)
+        assert err <= tol, (prec, err)
+
+
+@pytest.mark.parametrize("L,padded", [(256, 0), (256, 1), (512, 1), (1024, 0), (1024, 1), (2048, 0), (2048, 1)])
+def test_apply_large_fft_route(L, padded):
+    M = 2 * L if padded else L
+    gh = spectrum(M, 1e-4)
+    plan = binding.Plan(L, padded, gh)
+    plan.set_engine(binding.ENGINE_MULTIPASS)
+    d, x = _inputs(L, padded, 1)
+    ref = apply_fft(gh, d, x, padded)
+    banner("apply-large", L, padded)
+    y = dev(np.zeros((L, L)))
+    plan.apply(dev(d), dev(x), y, precision=binding.FP64)
+    assert relerr(host(y), ref) <= 1e-13
+    plan.apply(dev(d), dev(x), y, precision=binding.MIXED)
+    assert relerr(host(y), ref) <= 2e-6
+
+
+def test_apply_sampled_direct_full_size():
+    """L = 2048 zero-padded (M = 4096): 48 outputs by the direct O(L^2) sum."""
+    L, padded = 2048, 1
+    gh = spectrum(2 * L, 1e-4)
+    g = kernel_table(gh)
+    plan = binding.Plan(L, padded, gh)
+    d, x = _inputs(L, padded, 2)
+    banner("apply-sampled", L)
+    y = dev(np.zeros((L, L)))
+    plan.apply(dev(d), dev(x), y, precision=binding.FP64)
+    yh = host(y)
+    rng = np.random.default_rng(5)
+    rows = list(rng.integers(0, L, 40)) + [0, 0, L - 1, L - 1, 1, L // 2, L - 2, 7]
+    cols = list(rng.integers(0, L, 40)) + [0, L - 1, 0, L - 1, L // 2, 1, L - 2, 2040]
+    ref = apply_direct_at(g, d, x, padded, rows, cols)
+    scale = np.abs(x).max() * np.abs(g).sum()
+    assert np.max(np.abs(yh[rows, cols] - ref)) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("L", [8, 64, 512])
+def test_plane_waves_gpu(L):
+    eps = 1e-2
+    gh = spectrum(L, eps)
+    plan = binding.Plan(L, 0, gh)
+    plan.set_engine(binding.ENGINE_MULTIPASS)
+    dval = 0.75
+    d = np.full((L, L), dval)
+    i1, i2 = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    banner("plane-waves", L)
+    for (m, n) in [(0, 0), (1, 0), (0, 3), (L // 2, L // 2), (L - 1, 2), (3 % L, L // 2)]:
+        v = np.cos(2 * np.pi * ((m * i1 + n * i2) % L) / L)
+        y = dev(np.zeros((L, L)))
+        plan.apply(dev(d), dev(v), y)
+        np.testing.assert_allclose(host(y), (dval + gh[m, n]) * v, rtol=0, atol=1e-13 * (dval + gh.max()))
+
+
+def test_output_canary_and_alias_rejection():
+    import torch
+    L = 64
+    gh = spectrum(2 * L, 1e-3)
+    plan = binding.Plan(L, 1, gh)
+    d, x = _inputs(L, 1, 3)
+    buf = dev(np.full(L * L + 64, 12345.0))
+    y = buf[: L * L].view(L, L)
+    plan.apply(dev(d), dev(x), y)
+    tail = host(buf[L * L:])
+    assert np.all(tail == 12345.0)
+    xd = dev(x)
+    with pytest.raises(binding.FftcgError):
+        plan.apply(dev(d), xd, xd)
+    torch.cuda.synchronize()
+
+
+def test_stream_ordering_two_streams():
+    """Products on two streams with the same plan both match the oracle."""
+    import torch
+    L = 256
+    gh = spectrum(2 * L, 1e-3)
+    plan = binding.Plan(L, 1, gh)
+    d, x = _inputs(L, 1, 4)
+    ref = apply_fft(gh, d, x, 1)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    dd, xx = dev(d), dev(x)
+    ys = [torch.zeros((L, L), dtype=torch.float64, device="cuda") for _ in range(4)]
+    torch.cuda.synchronize()
+    for s, y in zip((s1, s2, s1, s2), ys):
+        with torch.cuda.stream(s):
+            plan.apply(dd, xx, y, stream=s)
+    torch.cuda.synchronize()
+    for y in ys:
+        assert relerr(host(y), ref) <= 1e-13

@@ -1,0 +1,178 @@
+"""Parity of fftcg_solve on the GPU against the oracle.
+
+* closed form (periodic, uniform d, constant b);
+* dense Cholesky on grids up to 16 x 16, periodic and padded, both modes;
+* periodic L = 64 instances (eps 1e-2) against the oracle's direct-route CG
+  run to stagnation: relative error <= 1e-10 (FP64);
+* padded L = 512 (eps 1e-3, 30% zeros in d) against the oracle's FFT-route
+  reference: <= 1e-10 (FP64) and <= 1e-8 (mixed);
+* padded L = 2048 (eps 1e-4, b ~ N(0,1)) in mixed precision: the error is
+  certified from the oracle's FP64 residual of the GPU solution (a property
+  that holds at any size), <= 1e-8;
+* edge cases: b = 0, maxit = 1, warm start at the solution, invalid d.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1305_3625_amd import binding
+from workloads import spectrum, periodic_instance, padded_instance, c1_instance, c2_instance, c3_instance
+from oracle import (kernel_table, solve_dense, reference_solve, apply_fft, lambda_lb, error_bound)
+from gpu_util import dev, host, relerr, banner
+
+pytestmark = pytest.mark.gpu
+
+MODES = [(binding.FP64, 1e-10, 1e-10), (binding.MIXED, 1e-8, 1e-8)]
+
+
+def _solve(plan, inst, prec, tol, x0=None, maxit=20000):
+    import torch
+    L = inst["L"]
+    x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, x0=x0, tol=tol, maxit=maxit, precision=prec,
+                      raise_on_error=False)
+    return host(x), info
+
+
+def test_closed_form():
+    L = 64
+    gh = spectrum(L, 1e-2)
+    plan = binding.Plan(L, 0, gh)
+    inst = dict(L=L, d=np.full((L, L), 0.8), b=np.full((L, L), 0.37))
+    for prec, tol, _ in MODES:
+        banner("closed-form", prec)
+        x, info = _solve(plan, inst, prec, tol)
+        assert info["status"] == binding.OK
+        np.testing.assert_allclose(x, 0.37 / (0.8 + 10.0), rtol=1e-12 if prec == binding.FP64 else 1e-8)
+        assert info["iterations"] <= 2
+
+
+@pytest.mark.parametrize("L", [2, 4, 8, 16])
+@pytest.mark.parametrize("padded", [0, 1])
+@pytest.mark.parametrize("mode", MODES)
+def test_cholesky(L, padded, mode):
+    prec, tol, bar = mode
+    inst = padded_instance(L, [60, L], eps=1e-3) if padded else periodic_instance(L, [61, L], eps=1e-2)
+    g = kernel_table(inst["ghat"])
+    xs = solve_dense(g, inst["d"], inst["b"], padded)
+    plan = binding.Plan(L, padded, inst["ghat"])
+    plan.set_engine(binding.ENGINE_MULTIPASS)
+    banner("cholesky", L, padded, prec)
+    x, info = _solve(plan, inst, prec, tol)
+    assert info["status"] == binding.OK, info
+    err = relerr(x, xs)
+    assert err <= bar, (err, info)
+    assert info["error_bound"] <= bar
+
+
+@pytest.mark.parametrize("s", [0, 1, 2, 3])
+def test_periodic_L64(s):
+    inst = c1_instance(s)
+    xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 0)
+    assert rinfo["bound"] < 1e-12
+    plan = binding.Plan(64, 0, inst["ghat"])
+    plan.set_engine(binding.ENGINE_MULTIPASS)
+    banner("periodic-L64", s)
+    x, info = _solve(plan, inst, binding.FP64, inst["tol"])
+    assert info["status"] == binding.OK
+    err = relerr(x, xr)
+    print(f"seed {s}: iters {info['iterations']} err {err:.3e} bound {info['error_bound']:.3e}")
+    assert err <= 1e-10
+    assert info["error_bound"] <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def padded512():
+    inst = c2_instance(0)
+    xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 1, route="fft")
+    assert rinfo["bound"] < 1e-12
+    return inst, xr
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_padded_L512(padded512, mode):
+    prec, tol, bar = mode
+    inst, xr = padded512
+    plan = binding.Plan(512, 1, inst["ghat"])
+    banner("padded-L512", prec)
+    x, info = _solve(plan, inst, prec, tol)
+    assert info["status"] == binding.OK
+    err = relerr(x, xr)
+    print(f"mode {prec}: iters {info['iterations']} checks {info['checks']} err {err:.3e} "
+          f"bound {info['error_bound']:.3e} ms {info['device_ms']:.2f}")
+    assert err <= bar
+
+
+def test_padded_L2048_mixed_certified():
+    inst = c3_instance(0)
+    plan = binding.Plan(2048, 1, inst["ghat"])
+    banner("padded-L2048-mixed")
+    x, info = _solve(plan, inst, binding.MIXED, inst["tol"])
+    assert info["status"] == binding.OK
+    r = inst["b"] - apply_fft(inst["ghat"], inst["d"], x, 1)
+    rn, xn = np.linalg.norm(r), np.linalg.norm(x)
+    bound = error_bound(rn, xn, lambda_lb(inst["ghat"], inst["d"]))
+    print(f"L2048 mixed: iters {info['iterations']} checks {info['checks']} oracle-certified bound {bound:.3e} "
+          f"relres {rn / np.linalg.norm(inst['b']):.3e} ms {info['device_ms']:.1f}")
+    assert bound <= 1e-8
+    assert rn / np.linalg.norm(inst["b"]) <= inst["tol"]
+
+
+def test_zero_rhs():
+    L = 32
+    inst = padded_instance(L, [62, 0])
+    inst["b"] = np.zeros((L, L))
+    plan = binding.Plan(L, 1, inst["ghat"])
+    import torch
+    x0 = dev(np.ones((L, L)))
+    for prec, tol, _ in MODES:
+        x = torch.full((L, L), 7.0, dtype=torch.float64, device="cuda")
+        info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, x0=x0, tol=tol, precision=prec)
+        assert info["status"] == binding.OK and info["iterations"] == 0
+        assert np.all(host(x) == 0.0)
+
+
+def test_maxit_one_returns_last_iterate():
+    L = 64
+    inst = padded_instance(L, [63, 0])
+    plan = binding.Plan(L, 1, inst["ghat"])
+    for prec, tol, _ in MODES:
+        x, info = _solve(plan, inst, prec, tol, maxit=1)
+        assert info["status"] == binding.ENOCONV
+        assert info["iterations"] == 1
+        # one CG step from zero: x = alpha b with alpha = b.b / b.Ab
+        from oracle import apply_direct
+        g = kernel_table(inst["ghat"])
+        Ab = apply_direct(g, inst["d"], inst["b"], 1)
+        alpha = np.sum(inst["b"] ** 2) / np.sum(inst["b"] * Ab)
+        assert relerr(x, alpha * inst["b"]) <= (1e-12 if prec == binding.FP64 else 1e-6)
+
+
+def test_warm_start_at_solution():
+    L = 32
+    inst = padded_instance(L, [64, 0])
+    g = kernel_table(inst["ghat"])
+    xs = solve_dense(g, inst["d"], inst["b"], 1)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    import torch
+    x = dev(xs)
+    info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, x0=x, tol=1e-10, precision=binding.FP64)
+    assert info["status"] == binding.OK
+    assert info["iterations"] <= 1
+    assert relerr(host(x), xs) <= 1e-12
+
+
+@pytest.mark.parametrize("bad", ["nan_d", "neg_d", "inf_b"])
+def test_invalid_data(bad):
+    L = 16
+    inst = padded_instance(L, [65, 0])
+    if bad == "nan_d":
+        inst["d"][3, 4] = np.nan
+    elif bad == "neg_d":
+        inst["d"][0, 0] = -0.5
+    else:
+        inst["b"][5, 5] = np.inf
+    plan = binding.Plan(L, 1, inst["ghat"])
+    for prec, tol, _ in MODES:
+        x, info = _solve(plan, inst, prec, tol)
+        assert info["status"] == binding.EINVAL
