@@ -81,6 +81,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise LibraryNotBuilt(f"{path} not built; run python -m paper_1305_3625_amd.build")
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading it
+    # first makes the library bind to that same runtime, so torch's device
+    # pointers and streams are valid inside the library; loading the library
+    # first would bring a second HIP runtime into the process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     U64P = ctypes.POINTER(ctypes.c_uint64)

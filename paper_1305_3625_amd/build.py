@@ -27,6 +27,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CXXFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # code objects loadable by the HIP runtime bundled with PyTorch
+    "-mcode-object-version=5",
     # packed FP32 instructions stay off (hand-written or compiler-made)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
@@ -72,7 +74,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
                 print(out)
     objs = [c[-1] for c in cmds]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread"])
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-fPIC", "-o", tmp,
+          *objs, "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -402,6 +402,10 @@ void fftcg::init_state(SolveState* h, const fftcg_plan_s* p, int precision, doub
     h->mixed = precision == FFTCG_MIXED ? 1 : 0;
     h->trigger_rr = 0.0;
     h->best_rt = INFINITY;
+    // mixed mode: residual replacement each time the FP32 recursive residual
+    // has fallen by 1e-2 since the last one (reliable updates)
+    h->delta2 = precision == FFTCG_MIXED ? 1e-4 : 0.0;
+    h->rho_ref = 0.0;
 }
 
 void fftcg::fill_slot(SlotDesc* h, const Workspace* w, double* x, const double* b, const double* d) {

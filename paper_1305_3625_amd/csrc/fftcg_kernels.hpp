@@ -163,7 +163,11 @@ struct ProCG {
         const bool progressed = iters > st->last_check_iter;
         const bool periodic = st->refresh > 0 && iters - st->last_check_iter >= st->refresh;
         const bool candidate = progressed && !(rr > st->trigger_rr);
-        const bool pause = iters >= st->maxit || candidate || periodic;
+        // reliable update: the recursive residual fell by sqrt(delta2) since the
+        // last replacement, the point after which it may drift from the true
+        // one by more than the working precision can carry
+        const bool reliable = progressed && rr <= st->delta2 * st->rho_ref;
+        const bool pause = iters >= st->maxit || candidate || periodic || reliable;
         if (pause) {
             if (blockIdx.x == 0 && threadIdx.x == 0) st->pause = 1;
             return false;
@@ -280,10 +284,11 @@ struct EpiCG {
 };
 
 // FP64 check: r64 = b - d x - C x; r (working precision) <- r64; partials of
-// |r64|^2, |x|^2, |b|^2, |r|^2, min d and the count of invalid inputs.
+// |r64|^2, |x|^2, |b|^2, |r|^2, min d, the count of invalid inputs and
+// |r64 - r_old|^2 (drift of the recursive residual it replaces).
 template <typename W>
 struct EpiCheck {
-    static constexpr int NACC = 6;
+    static constexpr int NACC = 7;
     using Gate = GateCheck;
     static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return GateCheck::ok(sd); }
     template <int L>
@@ -296,7 +301,12 @@ struct EpiCheck {
         const double r0 = bv.x - (dv.x * xv.x + c0);
         const double r1 = bv.y - (dv.y * xv.y + c1);
         const W w0 = (W)r0, w1 = (W)r1;
-        st2<W>(reinterpret_cast<W*>(sd.r) + idx, mkc(w0, w1));
+        W* rp = reinterpret_cast<W*>(sd.r) + idx;
+        if (sd.st->checks > 0) {  // the first check has no recursive residual yet
+            const cx<W> ro = ld2<W>(rp);
+            acc[6] += (r0 - (double)ro.x) * (r0 - (double)ro.x) + (r1 - (double)ro.y) * (r1 - (double)ro.y);
+        }
+        st2<W>(rp, mkc(w0, w1));
         acc[0] += r0 * r0 + r1 * r1;
         acc[1] += xv.x * xv.x + xv.y * xv.y;
         acc[2] += bv.x * bv.x + bv.y * bv.y;
@@ -508,9 +518,9 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
             const double s = block_sum<NT>(acc[0], red);
             if (tid == 0) part[PS_PQ * stride + blockIdx.x] = s;
         } else {
-            const int sets[6] = {PS_CHK_R, PS_CHK_X, PS_CHK_B, PS_CHK_RW, PS_CHK_DMIN, PS_CHK_BAD};
+            const int sets[7] = {PS_CHK_R, PS_CHK_X, PS_CHK_B, PS_CHK_RW, PS_CHK_DMIN, PS_CHK_BAD, PS_CHK_DIFF};
 #pragma unroll
-            for (int a = 0; a < 6; ++a) {
+            for (int a = 0; a < 7; ++a) {
                 const double s = (a == 4) ? block_min<NT>(acc[a], red) : block_sum<NT>(acc[a], red);
                 if (tid == 0) part[sets[a] * stride + blockIdx.x] = s;
             }
@@ -598,6 +608,7 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
     const double B = sum_partials<NT>(part + PS_CHK_B * stride, npart_chk, red);
     const double RW = sum_partials<NT>(part + PS_CHK_RW * stride, npart_chk, red);
     const double BAD = sum_partials<NT>(part + PS_CHK_BAD * stride, npart_chk, red);
+    const double DIFF = sum_partials<NT>(part + PS_CHK_DIFF * stride, npart_chk, red);
     double dmin = 1.0e300;
     for (int i = threadIdx.x; i < npart_chk; i += NT) dmin = fmin(dmin, part[PS_CHK_DMIN * stride + i]);
     dmin = block_min<NT>(dmin, red);
@@ -654,6 +665,11 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
                     st->restart = 1;
                     st->worse = 0;
                 }
+                // Keeping p after the replacement is sound only while the
+                // recursive residual still tracked the true one; past 10%
+                // drift the old direction is no longer conjugate, so restart.
+                if (!first && !(DIFF <= 0.01 * R)) st->restart = 1;
+                st->rho_ref = RW;
                 st->alpha = 0.0;
                 st->last_check_iter = st->iters;
                 st->last_rt = rt;

@@ -29,6 +29,8 @@ struct SolveState {
     double true_relres;  // last ||r||/||b||
     double bound;        // certified relative error bound at the last check
     double best_rt;      // smallest true residual seen
+    double rho_ref;      // r.r right after the last check (residual replacement)
+    double delta2;       // reliable-update threshold: check when r.r <= delta2 * rho_ref
     int iters;           // CG iterations done
     int maxit;
     int refresh;         // FP64 check period (0 = only at candidate convergence)
@@ -74,7 +76,8 @@ enum PartSet {
     PS_CHK_RW = 5,    // (working-precision r)^2
     PS_CHK_DMIN = 6,  // min d
     PS_CHK_BAD = 7,   // count of non-finite / negative inputs
-    NPART_SETS = 8
+    PS_CHK_DIFF = 8,  // |r64 - r_recursive|^2: drift of the recursive residual
+    NPART_SETS = 9
 };
 
 }  // namespace fftcg
