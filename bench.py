@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFT-convolution CG solver on one MI355X.
+
+Workload: mixed-precision solves on the zero-padded 2048 x 2048 grid
+(M = 4096), kernel eps = 1e-4, d ~ U(0.5, 1.5) with 30% zeros, b ~ N(0, 1),
+error target 1e-8 (three seeded instances, cycled).  A step is one complete
+solve: initial FP64 residual, every CG iteration (row R2C, column
+FFT*ghat*IFFT, row C2R + epilogue, update) and every FP64 check, until the
+certified stop rule holds.  Inputs are resident in HBM before timing.
+
+Printed as one JSON line: solves/s, matvecs/s, FFT GFLOP/s, effective HBM
+GB/s, the roofline of the dominant kernel (the column pass, timed live with
+HIP events on the stream it runs on), and the CPU oracle timed on a bounded
+sample on this host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FFT-CG solves/s + HBM GB/s at L=2048; served p50/p99 latency vs plain FP64"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_col_M4096_fp32_traffic.json")
+KERNEL_SOURCES = ["paper_1305_3625_amd/csrc/fftcg_kernels.hpp", "paper_1305_3625_amd/csrc/fftcg_dev.hpp",
+                  "paper_1305_3625_amd/csrc/engine_inst.hip"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_model(L, M):
+    """Algorithmic HBM bytes (mixed precision) of the passes on this grid."""
+    N = M // 2               # packed columns = complex row length
+    n = L * L
+    spec = 4 * N * (M // 2 + 1)      # FP32 quarter spectrum, read once per product
+    W = 8 * L * N                    # one sweep over the FP32 half spectrum
+    col = 2 * W + spec               # column pass: read W, read ghat, write W
+    it = (20 * n + W) + col + (W + 12 * n) + 12 * n   # row_fwd + col + row_inv + update
+    chk = (28 * n + 2 * W) + (4 * W + 2 * spec) + (2 * W + 32 * n)  # FP64 check passes
+    apply = (8 * n + W) + col + (W + 24 * n)          # fftcg_apply, FP32 operator
+    return dict(col=col, iteration=it, check=chk, apply=apply, per_column=16 * L + 4 * (M // 2 + 1))
+
+
+def fft_flops_nominal(M):
+    """5 n log2 n per complex 2-D transform of n = M^2 points, two per product."""
+    n = M * M
+    return 2 * 5 * n * math.log2(n)
+
+
+def cpu_baseline(inst, gpu_iters, max_seconds=20.0):
+    """The oracle's FP64 CG (eq. (3) numpy-FFT product, Listing 2 order) on
+    the same instance for a bounded number of iterations; scaled to solves/s
+    by the GPU's iteration count for that instance."""
+    import numpy as np
+    from oracle import apply_fft, cg
+    mv = lambda v: apply_fft(inst["ghat"], inst["d"], v, 1)  # noqa: E731
+    # one product alone sets the iteration budget
+    t0 = time.perf_counter()
+    mv(inst["b"])
+    t_mv = time.perf_counter() - t0
+    iters = max(1, min(8, int(max_seconds / max(t_mv, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    _, info = cg(mv, inst["b"], tol=0.0, maxit=iters)
+    t = time.perf_counter() - t0
+    per_it = t / max(1, info["iterations"])
+    return {
+        "value": 1.0 / (per_it * gpu_iters),
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{info['iterations']} iterations of the oracle's FP64 CG with its numpy-FFT product on "
+                   f"the padded L={inst['L']} instance (seed 0), {per_it:.2f} s/iteration, scaled by the "
+                   f"GPU solve's {gpu_iters} iterations; numpy's FFT and vector ops run on one core"),
+        "seconds": round(t + t_mv, 2),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--L", type=int, default=2048, help="grid side (default: the L=2048 workload)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle certification")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration under rocprofv3)")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (a single solve does not "
+                                   "shard profitably at L <= 2048; see DESIGN.md)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1305_3625_amd import binding
+    from workloads import c3_instance
+
+    torch.cuda.set_device(0)
+    L = a.L
+    M = 2 * L
+    insts = [c3_instance(s, L=L) for s in range(3)]
+    t0 = time.perf_counter()
+    plan = binding.Plan(L, 1, insts[0]["ghat"])
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda")  # noqa: E731
+    D = [dev(i["d"]) for i in insts]
+    B = [dev(i["b"]) for i in insts]
+    X = [torch.zeros((L, L), dtype=torch.float64, device="cuda") for _ in insts]
+    torch.cuda.synchronize()
+
+    def step(k):
+        j = k % len(insts)
+        return plan.solve(D[j], B[j], X[j], tol=1e-8, maxit=5000, precision=binding.MIXED)
+
+    for k in range(a.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        infos.append(step(k))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for inf in infos:
+        if inf["status"] != binding.OK:
+            raise SystemExit(f"solve failed: {inf}")
+    solves_per_s = a.steps / elapsed
+    iters = [inf["iterations"] for inf in infos]
+    checks = [inf["checks"] for inf in infos]
+    matvecs = sum(iters) + sum(checks)
+    bm = bytes_model(L, M)
+    bytes_total = sum(iters) * bm["iteration"] + sum(checks) * bm["check"]
+
+    # live per-pass timing of one product (HIP events on the launch stream)
+    y = torch.empty((L, L), dtype=torch.float64, device="cuda")
+    passes32 = plan.profile_apply(D[0], B[0], y, reps=30, precision=binding.MIXED)
+    passes64 = plan.profile_apply(D[0], B[0], y, reps=10, precision=binding.FP64)
+    t_col = passes32[1] * 1e-3
+    achieved = bm["col"] / t_col / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("L") == L:
+            traffic = tr.get("bytes_per_launch")
+
+    if a.copy_calib:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # oracle certification of each instance's GPU solution (FP64 residual)
+    oracle_bounds = None
+    if not a.no_oracle_check:
+        from oracle import apply_fft, lambda_lb, error_bound
+        oracle_bounds = []
+        for j, inst in enumerate(insts[: min(len(insts), a.steps)]):
+            x = X[j].cpu().numpy()
+            r = inst["b"] - apply_fft(inst["ghat"], inst["d"], x, 1)
+            oracle_bounds.append(error_bound(float(np.linalg.norm(r)), float(np.linalg.norm(x)),
+                                             lambda_lb(inst["ghat"], inst["d"])))
+
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(insts[0], infos[0]["iterations"])
+
+    out = {
+        "metric": METRIC,
+        "value": round(solves_per_s, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(elapsed / a.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"mixed-precision FFT-CG solve, zero-padded L={L} (M={M}), eps=1e-4, "
+                        f"d~U(0.5,1.5) with 30% zeros, b~N(0,1), relative error 1e-8 certified",
+            "L": L, "M": M, "padded": 1, "eps": 1e-4, "tol": 1e-8, "seeds": [[3, s] for s in range(3)],
+        },
+        "roofline": {
+            "kernel": "k_col (column pass: forward FFT, *ghat/M^2, inverse FFT, FP32)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": bm["col"],
+            "ms_per_launch": round(passes32[1], 5),
+        },
+        "cpu_baseline": cpu,
+        "iterations_mean": round(float(np.mean(iters)), 2),
+        "checks_mean": round(float(np.mean(checks)), 2),
+        "matvecs_per_s": round(matvecs / elapsed, 1),
+        "fft_gflops_nominal": round(matvecs / elapsed * fft_flops_nominal(M) / 1e9, 1),
+        "effective_GBps": round(bytes_total / elapsed / 1e9, 1),
+        "effective_frac": round(bytes_total / elapsed / 1e9 / HBM_PEAK_GBPS, 4),
+        "product_fp32_ms": [round(v, 5) for v in passes32],
+        "product_fp32_GBps": round(bm["apply"] / (sum(passes32) * 1e-3) / 1e9, 1),
+        "product_fp64_ms": [round(v, 5) for v in passes64],
+        "device_error_bound_max": max(inf["error_bound"] for inf in infos),
+        "oracle_error_bound_max": None if oracle_bounds is None else max(oracle_bounds),
+        "plan_ms": round(plan_ms, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -122,6 +122,15 @@ int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* devi
 int fftcg_apply(fftcg_plan_t plan, int precision, const double* d,
                 const double* x, double* y, void* stream);
 
+/* fftcg_profile_apply -- measurement aid: runs `reps` operator products
+ * exactly as fftcg_apply does, with HIP events on `stream` around each of
+ * the three passes (row forward, column, row inverse), and stores the mean
+ * device milliseconds of each pass in ms_per_pass[0..2] (HOST pointer).
+ * Blocks until done.  FFTCG_EINVAL for the fused engine (one kernel).     */
+int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d,
+                        const double* x, double* y, int reps,
+                        double* ms_per_pass, void* stream);
+
 /* fftcg_solve -- CG solve of (diag(d) + C) x = b (Sec. 3 Listing 2).
  *   d, b       DEVICE pointers, L*L doubles; d >= 0 and finite, b finite
  *              (checked on the device: FFTCG_EINVAL).
@@ -136,8 +145,8 @@ int fftcg_apply(fftcg_plan_t plan, int precision, const double* d,
  *   stream     hipStream_t used for all work; the call blocks until done.
  * Stopping: the residual rule AND the certified rule
  *   ||r|| <= tau * lambda_lb * ||x|| / (1 + tau),  lambda_lb = min d + min ghat,
- * which guarantees ||x - x*||/||x*|| <= tau, with tau = 1e-10 (FP64) or 1e-8
- * (MIXED).  b = 0 gives x = 0, FFTCG_OK and 0 iterations.                   */
+ * with tau = tol, which guarantees ||x - x*||/||x*|| <= tol (both checked on
+ * an FP64 true residual).  b = 0 gives x = 0, FFTCG_OK and 0 iterations.    */
 int fftcg_solve(fftcg_plan_t plan, int precision, const double* d,
                 const double* b, const double* x0, double tol, int maxit,
                 double* x, fftcg_info* info, void* stream);

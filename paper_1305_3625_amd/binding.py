@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD"
 # every symbol include/fftcg.h declares
 EXPORTS = [
     "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_info",
-    "fftcg_apply", "fftcg_solve", "fftcg_loadstep",
+    "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_get_stats", "fftcg_server_destroy",
     "fftcg_strerror", "fftcg_version",
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
         "fftcg_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                 ctypes.POINTER(S)]),
         "fftcg_apply": (I, [P, I, P, P, P, P]),
+        "fftcg_profile_apply": (I, [P, I, P, P, P, I, ctypes.POINTER(D), P]),
         "fftcg_solve": (I, [P, I, P, P, P, D, I, P, ctypes.POINTER(Info), P]),
         "fftcg_loadstep": (I, [P, P, P, P, ctypes.POINTER(I), P]),
         "fftcg_server_create": (I, [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]),
@@ -196,6 +197,15 @@ class Plan:
         if st != OK:
             raise FftcgError(st, "fftcg_apply")
         return y
+
+    def profile_apply(self, d, x, y, reps=20, precision=FP64, stream=None):
+        """Mean device ms of the three passes of one product (HIP events)."""
+        ms = (ctypes.c_double * 3)()
+        st = load().fftcg_profile_apply(self.h, precision, _ptr(d), _ptr(x), _ptr(y), int(reps), ms,
+                                        _stream(stream))
+        if st != OK:
+            raise FftcgError(st, "fftcg_profile_apply")
+        return [ms[0], ms[1], ms[2]]
 
     def solve(self, d, b, x, x0=None, tol=1e-10, maxit=10000, precision=FP64, stream=None,
               raise_on_error=True):

@@ -27,6 +27,9 @@ struct EngineOps {
     // y = d x + C x, precision 0 = FP64, 1 = FP32 operator
     void (*apply)(int prec, const PlanTabs& t, const double* d, const double* x, double* y,
                   void* W, hipStream_t s);
+    // one pass of an operator product: 0 row_fwd, 1 col, 2 row_inv
+    void (*apply_pass)(int prec, int pass, const PlanTabs& t, const double* d, const double* x, double* y,
+                       void* W, hipStream_t s);
     // one CG iteration for nslots slots (row_fwd, col, row_inv, update)
     void (*iter)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
                  hipStream_t s);

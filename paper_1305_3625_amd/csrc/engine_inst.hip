@@ -41,7 +41,8 @@ Tab<double> tab_of<double>(const PlanTabs& t) {
 }
 
 template <typename T>
-void apply_t(const PlanTabs& pt, const double* d, const double* x, double* y, void* W, hipStream_t s) {
+void apply_pass_t(int pass, const PlanTabs& pt, const double* d, const double* x, double* y, void* W,
+                  hipStream_t s) {
     constexpr int RT = G<T>::ROW_THREADS, CT = G<T>::COL_THREADS;
     ByVal sv;
     memset(&sv.s, 0, sizeof(SlotDesc));
@@ -51,11 +52,27 @@ void apply_t(const PlanTabs& pt, const double* d, const double* x, double* y, vo
     sv.s.W = W;
     sv.s.active = 1;
     const Tab<T> tab = tab_of<T>(pt);
-    hipLaunchKernelGGL((k_row_fwd<T, M, PAD, ProApply<T>, ByVal, RT>), dim3(G<T>::ROW_BLOCKS), dim3(RT), 0, s,
-                       tab, sv, 0, 0);
-    hipLaunchKernelGGL((k_col<T, M, PAD, GateAlways, ByVal, CT>), dim3(G<T>::NTILE), dim3(CT), 0, s, tab, sv);
-    hipLaunchKernelGGL((k_row_inv<T, M, PAD, EpiApply<T>, ByVal, RT>), dim3(G<T>::ROW_BLOCKS), dim3(RT), 0, s,
-                       tab, sv, 0);
+    if (pass == 0)
+        hipLaunchKernelGGL((k_row_fwd<T, M, PAD, ProApply<T>, ByVal, RT>), dim3(G<T>::ROW_BLOCKS), dim3(RT), 0,
+                           s, tab, sv, 0, 0);
+    else if (pass == 1)
+        hipLaunchKernelGGL((k_col<T, M, PAD, GateAlways, ByVal, CT>), dim3(G<T>::NTILE), dim3(CT), 0, s, tab, sv);
+    else
+        hipLaunchKernelGGL((k_row_inv<T, M, PAD, EpiApply<T>, ByVal, RT>), dim3(G<T>::ROW_BLOCKS), dim3(RT), 0,
+                           s, tab, sv, 0);
+}
+
+template <typename T>
+void apply_t(const PlanTabs& pt, const double* d, const double* x, double* y, void* W, hipStream_t s) {
+    for (int pass = 0; pass < 3; ++pass) apply_pass_t<T>(pass, pt, d, x, y, W, s);
+}
+
+void apply_pass_fn(int prec, int pass, const PlanTabs& pt, const double* d, const double* x, double* y, void* W,
+                   hipStream_t s) {
+    if (prec == 0)
+        apply_pass_t<double>(pass, pt, d, x, y, W, s);
+    else
+        apply_pass_t<float>(pass, pt, d, x, y, W, s);
 }
 
 void apply_fn(int prec, const PlanTabs& pt, const double* d, const double* x, double* y, void* W,
@@ -119,6 +136,7 @@ const EngineOps kOps = {M,
                         G<double>::ROW_BLOCKS,
                         g4_blocks(),
                         &apply_fn,
+                        &apply_pass_fn,
                         &iter_fn,
                         &check_fn};
 

@@ -135,9 +135,17 @@ __host__ __device__ constexpr int fft_ns(int N, bool rev, int s) {
     return s == 0 ? 1 : fft_ns(N, rev, s - 1) * fft_radix(N, rev, s - 1);
 }
 
-// LDS layout: complex word w = pos * TT + col, stored at w + (w >> SH) * PADW.
+// LDS layout: complex word w = pos * TT + col, stored at w + (w >> SH) * PADW,
+// SH = log2(16 TT): PADW words of padding after every 16 positions, so the
+// stride-R writes of the first stage do not all hit one bank.
+//
+// A run of R positions pos0 + r S has compile-time offsets from the first
+// element whenever S is a multiple of 16 (the padding grows by S/16 spans
+// per step) or the whole run stays inside one 16-position span (no padding
+// in between): the accesses then use immediate LDS offsets.
 template <typename T, int TT, int SH, int PADW>
 struct LdsLay {
+    static_assert((1 << SH) == 16 * TT, "padding span is 16 positions");
     cx<T>* base;
     int col;
     __device__ __forceinline__ int phys(int pos) const {
@@ -147,7 +155,66 @@ struct LdsLay {
     __device__ __forceinline__ void st(int pos, cx<T> v) const { base[phys(pos)] = v; }
     __device__ __forceinline__ cx<T> ld(int pos) const { return base[phys(pos)]; }
     static constexpr int words(int n) { return n * TT + ((n * TT) >> SH) * PADW + PADW; }
+    // offset in words between run elements r and 0, when it is a constant
+    template <int S, int R>
+    static constexpr int run_step() {
+        return S % 16 == 0 ? S * TT + (S / 16) * PADW : (S * R <= 16 ? S * TT : -1);
+    }
+    // v[r] -> position pos0 + r S, r < R (runs with S R <= 16 must start so
+    // that they stay inside one span, as every caller's runs do)
+    template <int R, int S>
+    __device__ __forceinline__ void st_run(int pos0, const cx<T>* v) const {
+        constexpr int D = run_step<S, R>();
+        if constexpr (D >= 0) {
+            cx<T>* p = base + phys(pos0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r * D] = v[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) st(pos0 + r * S, v[r]);
+        }
+    }
+    template <int R, int S>
+    __device__ __forceinline__ void ld_run(int pos0, cx<T>* v) const {
+        constexpr int D = run_step<S, R>();
+        if constexpr (D >= 0) {
+            const cx<T>* p = base + phys(pos0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = p[r * D];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = ld(pos0 + r * S);
+        }
+    }
 };
+
+// v[r] *= w^(r m), r = 1..R-1, with w^m = tw[m] = exp(-2 pi i m / MTAB) (DIR
+// = -1) or its conjugate (DIR = +1).  Four table reads (m, 2m, 4m, 8m); the
+// other powers are products of at most three of them.
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void twiddle_run(cx<T>* v, const cx<T>* __restrict__ tw, int m) {
+    cx<T> p[16];
+    p[1] = tw[m];
+    if constexpr (R > 2) p[2] = tw[2 * m];
+    if constexpr (R > 4) p[4] = tw[4 * m];
+    if constexpr (R > 8) p[8] = tw[8 * m];
+    if constexpr (R > 3) p[3] = cmul(p[1], p[2]);
+    if constexpr (R > 5) {
+        p[5] = cmul(p[1], p[4]);
+        p[6] = cmul(p[2], p[4]);
+        p[7] = cmul(p[3], p[4]);
+    }
+    if constexpr (R > 9) {
+#pragma unroll
+        for (int r = 1; r < 8; ++r) p[8 + r] = cmul(p[r], p[8]);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        cx<T> w = p[r];
+        if (DIR > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+    }
+}
 
 // Runs stages S.. of the length-N transform held by this thread (index j of
 // N/E threads).  On entry v[u R + r] holds position (j + u P) + r N / R_S.
@@ -165,14 +232,8 @@ __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j,
     for (int u = 0; u < NB; ++u) {
         const int b = j + u * P;
         if constexpr (NS > 1) {
-            const int k = b & (NS - 1);
             constexpr int STEP = MTAB / (NS * R);
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                cx<T> w = tw[k * r * STEP];
-                if (DIR > 0) w.y = -w.y;
-                v[u * R + r] = cmul(v[u * R + r], w);
-            }
+            twiddle_run<T, R, DIR>(v + u * R, tw, (b & (NS - 1)) * STEP);
         }
         dft<T, R, DIR, HALF_IN && S == 0>(v + u * R);
     }
@@ -181,18 +242,13 @@ __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j,
         for (int u = 0; u < NB; ++u) {
             const int b = j + u * P;
             const int base = (b / NS) * NS * R + (b & (NS - 1));
-#pragma unroll
-            for (int r = 0; r < R; ++r) lay.st(base + r * NS, v[u * R + r]);
+            lay.template st_run<R, NS>(base, v + u * R);
         }
         __syncthreads();
         constexpr int R2 = fft_radix(N, REV, S + 1);
         constexpr int NB2 = E / R2;
 #pragma unroll
-        for (int u = 0; u < NB2; ++u) {
-            const int b = j + u * P;
-#pragma unroll
-            for (int r = 0; r < R2; ++r) v[u * R2 + r] = lay.ld(b + r * (N / R2));
-        }
+        for (int u = 0; u < NB2; ++u) lay.template ld_run<R2, N / R2>(j + u * P, v + u * R2);
         __syncthreads();
         stages<T, N, MTAB, DIR, REV, HALF_IN, S + 1, Lay>(v, lay, j, tw);
     }

@@ -366,6 +366,44 @@ extern "C" int fftcg_apply(fftcg_plan_t plan, int precision, const double* d, co
     return FFTCG_OK;
 }
 
+extern "C" int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d, const double* x, double* y,
+                                   int reps, double* ms_per_pass, void* stream) {
+    if (!plan || !d || !x || !y || !ms_per_pass || reps < 1) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    const size_t nb = (size_t)plan->L * plan->L * 8;
+    if (overlap(y, x, nb) || overlap(y, d, nb)) return FFTCG_EINVAL;
+    if (!plan->ops || plan_engine(plan) == FFTCG_ENGINE_FUSED) return FFTCG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(plan->mu);
+    hipEvent_t ev[4];
+    for (int i = 0; i < 4; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) return FFTCG_EDEVICE;
+    int rc = FFTCG_OK;
+    double acc[3] = {0, 0, 0};
+    if (hipStreamWaitEvent(s, plan->apply_ev, 0) != hipSuccess) rc = FFTCG_EDEVICE;
+    for (int it = 0; it < reps && rc == FFTCG_OK; ++it) {
+        (void)hipEventRecord(ev[0], s);
+        for (int pass = 0; pass < 3; ++pass) {
+            plan->ops->apply_pass(precision, pass, plan->tabs, d, x, y, plan->apply_W, s);
+            (void)hipEventRecord(ev[pass + 1], s);
+        }
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(ev[3]) != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        for (int pass = 0; pass < 3; ++pass) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[pass], ev[pass + 1]);
+            acc[pass] += ms;
+        }
+    }
+    (void)hipEventRecord(plan->apply_ev, s);
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc == FFTCG_OK)
+        for (int pass = 0; pass < 3; ++pass) ms_per_pass[pass] = acc[pass] / reps;
+    return rc;
+}
+
 // ---- solve -------------------------------------------------------------------
 Workspace* fftcg::plan_acquire(fftcg_plan_s* p) {
     std::lock_guard<std::mutex> lk(p->mu);
@@ -392,7 +430,7 @@ void fftcg::plan_release(fftcg_plan_s* p, Workspace* w) {
 void fftcg::init_state(SolveState* h, const fftcg_plan_s* p, int precision, double tol, int maxit, int refresh) {
     memset(h, 0, sizeof(SolveState));
     h->tol = tol;
-    h->tau = precision == FFTCG_MIXED ? 1e-8 : 1e-10;
+    h->tau = tol;  // certified relative error target = the residual tolerance
     h->gmin = p->gmin;
     h->maxit = maxit;
     h->refresh = precision == FFTCG_MIXED ? refresh : 0;

@@ -66,6 +66,27 @@ struct Geo {
     static constexpr int MH = M / 2 + 1;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Row blocks that share 128-byte lines of W must run on the same XCD,
+// so block b works on logical block (b % 8) * (G / 8) + b / 8: each XCD gets
+// a contiguous range of rows, visited in order.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    if (G < 16 || (G & 7)) return b;
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+// Status words for the host (pinned, device-visible): [1] status, [2] the
+// solve's generation, then [0] done with release order, so a host that sees
+// done also sees the status and can tell a finished solve from an earlier
+// occupant of the same slot.
+__device__ __forceinline__ void publish_status(const SlotDesc& sd, int done, int status, int gen, int iters) {
+    if (!sd.host_status) return;
+    __hip_atomic_store(sd.host_status + 1, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(sd.host_status + 2, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(sd.host_status + 3, iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(sd.host_status, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ---- slot access policies -------------------------------------------------
 struct ByPtr {
     const SlotDesc* p;
@@ -332,7 +353,8 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     if (!Pro::begin(sd, sh, npart_rr, stride)) return;
     const int tid = threadIdx.x;
     const int rl = tid / P, j = tid % P;
-    const int row = blockIdx.x * RPW + rl;
+    const int rb = xcd_remap(blockIdx.x, gridDim.x);
+    const int row = rb * RPW + rl;
     LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
     cx<T> v[E];
     constexpr int NSTG = fft_nstages(N);
@@ -349,9 +371,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
     constexpr int RL = NSTG > 0 ? fft_radix(N, false, NSTG - 1) : 1;
 #pragma unroll
-    for (int u = 0; u < E / RL; ++u)
-#pragma unroll
-        for (int r = 0; r < RL; ++r) lay.st((j + u * P) + r * (N / RL), v[u * RL + r]);
+    for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, N / RL>(j + u * P, v + u * RL);
     __syncthreads();
     cx<T>* Wb = reinterpret_cast<cx<T>*>(sd.W);
 #pragma unroll
@@ -372,7 +392,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
             const cx<T> wd = cmul(tab.tw[k], d1);
             out = mkc(T(0.5) * (s1.x + wd.y), T(0.5) * (s1.y - wd.x));
         }
-        Wb[((size_t)kt * L + blockIdx.x * RPW + il) * TT + kk] = out;
+        Wb[((size_t)kt * L + rb * RPW + il) * TT + kk] = out;
     }
 }
 
@@ -408,9 +428,7 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
         // part): result(m) = s(m) W(m) + t(m) conj(W(M - m)),
         // s = (g0 + gN)/2, t = (g0 - gN)/2.
 #pragma unroll
-        for (int u = 0; u < E / RL; ++u)
-#pragma unroll
-            for (int r = 0; r < RL; ++r) lay.st((j + u * P) + r * (M / RL), v[u * RL + r]);
+        for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, M / RL>(j + u * P, v + u * RL);
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < E / RL; ++u)
@@ -463,7 +481,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
     if (!Epi::begin(sd)) return;
     const int tid = threadIdx.x;
     const int rl = tid / P, j = tid % P;
-    const int row0 = blockIdx.x * RPW;
+    const int row0 = xcd_remap(blockIdx.x, gridDim.x) * RPW;
     const cx<T>* Wb = reinterpret_cast<const cx<T>*>(sd.W);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -479,23 +497,31 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
     cx<T> v[E];
     constexpr int NSTG = fft_nstages(N);
     constexpr int R1 = NSTG > 0 ? fft_radix(N, true, 0) : 1;
+    constexpr int S1 = N / R1;
 #pragma unroll
-    for (int u = 0; u < E / R1; ++u)
+    for (int u = 0; u < E / R1; ++u) {
+        // Y at k = jj + r S1, and the partners N - k = (S1 - jj) + (R1-1-r) S1
+        // (jj > 0) or (R1 - r) S1 (jj == 0), read as two runs
+        const int jj = j + u * P;
+        cx<T> A[R1], Bv[R1];
+        lay.template ld_run<R1, S1>(jj, A);
+        lay.template ld_run<R1, S1>(jj == 0 ? 0 : S1 - jj, Bv);
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
-            const int k = (j + u * P) + r * (N / R1);
-            const cx<T> Y = lay.ld(k);
+            const int k = jj + r * S1;
+            const cx<T> Y = A[r];
             cx<T> Z;
             if (k == 0) {
                 Z = mkc(Y.x + Y.y, Y.x - Y.y);
             } else {
-                const cx<T> B = conjc(lay.ld(N - k));
+                const cx<T> B = conjc(jj == 0 ? Bv[(R1 - r) % R1] : Bv[R1 - 1 - r]);
                 const cx<T> s1 = Y + B, d1 = Y - B;
                 const cx<T> wd = cmul(conjc(tab.tw[k]), d1);
                 Z = mkc(s1.x - wd.y, s1.y + wd.x);
             }
             v[u * R1 + r] = Z;
         }
+    }
     __syncthreads();
     fft_run<T, N, M, +1, true, false>(v, lay, j, tab.tw);
     constexpr int RL = NSTG > 0 ? fft_radix(N, true, NSTG - 1) : 1;
@@ -542,10 +568,7 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->status = ST_EBREAKDOWN;
             st->done = 1;
-            if (sd.host_status) {
-                __hip_atomic_store(sd.host_status + 1, ST_EBREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(sd.host_status, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
+            publish_status(sd, 1, ST_EBREAKDOWN, st->gen, st->iters);
         }
         return;
     }
@@ -596,10 +619,7 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
     if (!sd.active) return;
     SolveState* st = sd.st;
     if (st->done || !st->pause) {
-        if (threadIdx.x == 0 && sd.host_status) {
-            __hip_atomic_store(sd.host_status + 1, st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(sd.host_status, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        if (threadIdx.x == 0) publish_status(sd, st->done, st->status, st->gen, st->iters);
         return;
     }
     const double* part = sd.part;
@@ -679,10 +699,7 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
             }
         }
         s_update = update;
-        if (sd.host_status) {
-            __hip_atomic_store(sd.host_status + 1, st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(sd.host_status, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        publish_status(sd, st->done, st->status, st->gen, st->iters);
     }
     __syncthreads();
     if (s_update) {

@@ -44,7 +44,7 @@ struct SolveState {
     int iters_literal;   // iteration count when the residual rule first held
     int bzero;           // b == 0 detected
     int mixed;           // 1: working vectors are FP32
-    int pad_;
+    int gen;             // generation of this solve (published with the status)
 };
 
 // Per-slot descriptor (device memory).

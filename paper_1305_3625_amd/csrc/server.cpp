@@ -1,14 +1,584 @@
-// Continuous-batching server (scheduler under construction: creation fails).
-#include "fftcg.h"
+// Continuous-batching solve server.
+//
+// Requests are grouped into classes by (plan, precision): one grid size and
+// one arithmetic each.  Every class has a pool of slots; a slot owns the
+// device vectors of one in-flight solve.  The scheduler thread repeatedly,
+// for every class:
+//   retire  - a slot whose solve finished (status word carrying the slot's
+//             current generation) copies x back to the request's pinned
+//             buffer; a load-stepped sequence instead runs the load step on
+//             the device and restarts the slot from the previous x;
+//   admit   - queued requests (FIFO per class) take free slots; new slots are
+//             allocated while the device memory held by all slots stays
+//             within the budget (idle slots of other classes are released
+//             when a class has none);
+//   step    - one chunk of CG iterations plus an FP64 check is launched over
+//             all slots of the class at once (gridDim.y = slot), on the
+//             class's own stream, so classes overlap on the GPU.
+// A slot's arithmetic does not depend on the other slots (per-slot
+// reductions in a fixed order), so a request gives bitwise the same x alone
+// and in any mix.  Host <-> device copies happen only at admission and
+// retirement.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
 
-extern "C" int fftcg_server_create(const fftcg_server_opts*, fftcg_server_t*) { return FFTCG_EDEVICE; }
-extern "C" int fftcg_submit(fftcg_server_t, fftcg_plan_t, int, const double*, const double*, const double*, double,
-                            int, uint64_t*) { return FFTCG_EINVAL; }
-extern "C" int fftcg_submit_sequence(fftcg_server_t, fftcg_plan_t, int, const double*, const double*,
-                                     const double*, double, int, int, uint64_t*) { return FFTCG_EINVAL; }
-extern "C" int fftcg_poll(fftcg_server_t, uint64_t, double*, fftcg_info*) { return FFTCG_EINVAL; }
-extern "C" int fftcg_poll_sequence(fftcg_server_t, uint64_t, double*, int*, int*, fftcg_info*) {
-    return FFTCG_EINVAL;
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "engine.hpp"
+#include "fftcg.h"
+#include "fftcg_internal.hpp"
+
+using namespace fftcg;
+
+namespace {
+
+constexpr int kMaxSteps = 1024;  // capacity of a slot's broken-index buffer
+
+struct Request {
+    uint64_t ticket = 0;
+    fftcg_plan_s* plan = nullptr;
+    int precision = 0;
+    double tol = 0;
+    int maxit = 0;
+    int steps = 0;  // 0: one solve; > 0: load-stepped sequence
+    size_t n = 0;
+    double* pin_in = nullptr;  // pinned staging: d, b, x0, t
+    double* pin_x = nullptr;   // pinned result
+    int* pin_broken = nullptr; // pinned sequence result
+    bool has_x0 = false;
+    int status = FFTCG_PENDING;
+    fftcg_info info{};
+    std::vector<int> step_iters;
+    bool done = false;
+};
+
+struct Slot {
+    std::unique_ptr<Workspace> ws;
+    double* x = nullptr;
+    double* b = nullptr;
+    double* d = nullptr;
+    double* t = nullptr;
+    int* broken = nullptr;            // device, one entry per step
+    SolveState* pin_state = nullptr;  // pinned staging of the state
+    Request* req = nullptr;
+    int gen = 0;
+    int step = 0;
+    bool retiring = false;
+    hipEvent_t ev_retire = nullptr;
+};
+
+struct Class {
+    fftcg_plan_s* plan = nullptr;
+    int precision = 0;
+    hipStream_t stream = nullptr;
+    std::vector<std::unique_ptr<Slot>> slots;
+    SlotDesc* d_table = nullptr;  // device slot table (max_slots entries)
+    SlotDesc* h_table = nullptr;  // pinned mirror
+    int* h_status = nullptr;      // pinned: {done, status, gen, iters} per slot
+    int* d_status = nullptr;
+    std::deque<Request*> pending;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int inflight = 0;  // chunks launched and not yet seen complete
+    int next_ev = 0;
+    size_t footprint = 0;  // device bytes per slot
+};
+
+}  // namespace
+
+struct fftcg_server_s {
+    fftcg_server_opts opts{};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread thread;
+    std::atomic<bool> stop{false};
+    std::map<std::pair<fftcg_plan_s*, int>, std::unique_ptr<Class>> classes;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+    uint64_t next_ticket = 1;
+    std::atomic<size_t> bytes_in_use{0};
+    std::atomic<int> in_flight{0};
+    int queued = 0;
+    fftcg_server_stats stats{};
+};
+
+namespace {
+
+size_t slot_footprint(const fftcg_plan_s* p) {
+    const size_t n = (size_t)p->L * p->L;
+    return workspace_bytes(p->L, p->M, p->stride) + 4 * n * 8 + sizeof(int) * kMaxSteps + 4096;
 }
-extern "C" int fftcg_server_get_stats(fftcg_server_t, fftcg_server_stats*) { return FFTCG_EINVAL; }
-extern "C" int fftcg_server_destroy(fftcg_server_t) { return FFTCG_EINVAL; }
+
+void free_slot_memory(Slot* s) {
+    double* dv[] = {s->x, s->b, s->d, s->t};
+    for (double* v : dv)
+        if (v) (void)hipFree(v);
+    if (s->broken) (void)hipFree(s->broken);
+    if (s->pin_state) (void)hipHostFree(s->pin_state);
+    if (s->ev_retire) (void)hipEventDestroy(s->ev_retire);
+    s->x = s->b = s->d = s->t = nullptr;
+    s->broken = nullptr;
+    s->pin_state = nullptr;
+    s->ev_retire = nullptr;
+    s->ws.reset();
+}
+
+void upload_entry(Class* c, int idx) {
+    (void)hipMemcpyAsync(c->d_table + idx, c->h_table + idx, sizeof(SlotDesc), hipMemcpyHostToDevice, c->stream);
+}
+
+// Releases idle slots at the end of other classes' pools until `need` more
+// bytes fit in the budget (scheduler thread).  hipFree waits for the device.
+void reclaim(fftcg_server_s* srv, Class* except, size_t need) {
+    std::vector<Class*> cls;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (auto& kv : srv->classes)
+            if (kv.second.get() != except) cls.push_back(kv.second.get());
+    }
+    for (Class* c : cls) {
+        while (!c->slots.empty() && srv->bytes_in_use.load() + need > srv->opts.memory_budget) {
+            Slot* s = c->slots.back().get();
+            if (s->req) break;
+            (void)hipStreamSynchronize(c->stream);
+            free_slot_memory(s);
+            c->slots.pop_back();
+            srv->bytes_in_use.fetch_sub(c->footprint);
+        }
+        if (srv->bytes_in_use.load() + need <= srv->opts.memory_budget) return;
+    }
+}
+
+// Adds one slot to class c; false when at max_slots, over budget, or the
+// allocation fails.
+bool add_slot(fftcg_server_s* srv, Class* c) {
+    if ((int)c->slots.size() >= srv->opts.max_slots) return false;
+    if (srv->bytes_in_use.load() + c->footprint > srv->opts.memory_budget) {
+        if (!c->slots.empty()) return false;
+        reclaim(srv, c, c->footprint);
+        if (srv->bytes_in_use.load() + c->footprint > srv->opts.memory_budget) return false;
+    }
+    auto s = std::make_unique<Slot>();
+    const fftcg_plan_s* p = c->plan;
+    const size_t n = (size_t)p->L * p->L;
+    s->ws.reset(new Workspace());
+    bool ok = s->ws->init(p->L, p->M, p->stride) == FFTCG_OK;
+    ok = ok && hipMalloc(&s->x, n * 8) == hipSuccess && hipMalloc(&s->b, n * 8) == hipSuccess &&
+         hipMalloc(&s->d, n * 8) == hipSuccess && hipMalloc(&s->t, n * 8) == hipSuccess &&
+         hipMalloc(&s->broken, sizeof(int) * kMaxSteps) == hipSuccess &&
+         hipHostMalloc((void**)&s->pin_state, sizeof(SolveState), hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&s->ev_retire, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        free_slot_memory(s.get());
+        return false;
+    }
+    srv->bytes_in_use.fetch_add(c->footprint);
+    const int idx = (int)c->slots.size();
+    fill_slot(&c->h_table[idx], s->ws.get(), s->x, s->b, s->d);
+    c->h_table[idx].host_status = c->d_status + 4 * idx;
+    c->h_table[idx].active = 0;
+    memset(c->h_status + 4 * idx, 0, 4 * sizeof(int));
+    c->slots.push_back(std::move(s));
+    upload_entry(c, idx);
+    return true;
+}
+
+int make_class(fftcg_server_s* srv, fftcg_plan_s* plan, int precision, Class** out) {
+    auto c = std::make_unique<Class>();
+    c->plan = plan;
+    c->precision = precision;
+    c->footprint = slot_footprint(plan);
+    const int ms = srv->opts.max_slots;
+    bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc((void**)&c->d_table, sizeof(SlotDesc) * ms) == hipSuccess &&
+              hipHostMalloc((void**)&c->h_table, sizeof(SlotDesc) * ms, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&c->h_status, sizeof(int) * 4 * ms,
+                            hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&c->d_status, c->h_status, 0) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        // partial class: released by destroy_class through the map
+        srv->classes[{plan, precision}] = std::move(c);
+        return FFTCG_EDEVICE;
+    }
+    memset(c->h_table, 0, sizeof(SlotDesc) * ms);
+    memset(c->h_status, 0, sizeof(int) * 4 * ms);
+    *out = c.get();
+    srv->classes[{plan, precision}] = std::move(c);
+    return FFTCG_OK;
+}
+
+void destroy_class(Class* c) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& s : c->slots) free_slot_memory(s.get());
+    if (c->d_table) (void)hipFree(c->d_table);
+    if (c->h_table) (void)hipHostFree(c->h_table);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    for (int i = 0; i < 2; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+// (Re)starts the solve in slot idx with a fresh state of a new generation;
+// the check at the end of the next chunk computes r = b - A x from the slot's
+// x (zero, the caller's x0, or the previous step's solution).
+void start_solve(Class* c, int idx) {
+    Slot* s = c->slots[idx].get();
+    Request* q = s->req;
+    s->gen += 1;
+    init_state(s->pin_state, c->plan, q->precision, q->tol, q->maxit, 50);
+    s->pin_state->gen = s->gen;
+    (void)hipMemcpyAsync(s->ws->st, s->pin_state, sizeof(SolveState), hipMemcpyHostToDevice, c->stream);
+    if (q->precision == FFTCG_MIXED) {
+        (void)hipMemsetAsync(s->ws->e, 0, q->n * 4, c->stream);
+        launch_to_f32(s->d, s->ws->d32, (int)q->n, c->stream);
+    }
+}
+
+void admit(Class* c, Request* q, int idx) {
+    Slot* s = c->slots[idx].get();
+    s->req = q;
+    s->step = 0;
+    s->retiring = false;
+    const size_t n = q->n;
+    const double* pin = q->pin_in;
+    hipStream_t st = c->stream;
+    (void)hipMemcpyAsync(s->d, pin, n * 8, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(s->b, pin + n, n * 8, hipMemcpyHostToDevice, st);
+    if (q->has_x0)
+        (void)hipMemcpyAsync(s->x, pin + 2 * n, n * 8, hipMemcpyHostToDevice, st);
+    else
+        (void)hipMemsetAsync(s->x, 0, n * 8, st);
+    if (q->steps > 0) (void)hipMemcpyAsync(s->t, pin + 3 * n, n * 8, hipMemcpyHostToDevice, st);
+    start_solve(c, idx);
+    c->h_table[idx].active = 1;
+    upload_entry(c, idx);
+}
+
+// Called with srv->mu held.
+void finish_request(fftcg_server_s* srv, Request* q, int status, const SolveState& st) {
+    q->status = status;
+    q->info.status = status;
+    q->info.iterations = st.iters;
+    q->info.iterations_literal = st.iters_literal;
+    q->info.checks = st.checks;
+    q->info.true_relres = st.true_relres;
+    q->info.error_bound = st.bound;
+    q->info.lambda_lb = st.lam_lb;
+    q->info.device_ms = 0.0;
+    q->done = true;
+    if (status == FFTCG_OK || status == FFTCG_ENOCONV)
+        srv->stats.completed += 1;
+    else if (status == FFTCG_ECANCELED)
+        srv->stats.canceled += 1;
+    else
+        srv->stats.failed += 1;
+    q->plan->refs.fetch_sub(1);
+}
+
+// Scheduler work for one class; true while it has queued or running work.
+bool progress(fftcg_server_s* srv, Class* c) {
+    // chunks that completed
+    while (c->inflight > 0) {
+        const int e = (c->next_ev - c->inflight + 2) & 1;
+        if (hipEventQuery(c->ev[e]) != hipSuccess) break;
+        c->inflight -= 1;
+    }
+    const int ns = (int)c->slots.size();
+    // retirements whose copies have landed
+    for (int i = 0; i < ns; ++i) {
+        Slot* s = c->slots[i].get();
+        if (!s->req || !s->retiring || hipEventQuery(s->ev_retire) != hipSuccess) continue;
+        Request* q = s->req;
+        const SolveState st = *s->pin_state;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (q->steps > 0) q->step_iters.push_back(st.iters);
+            finish_request(srv, q, st.status, st);
+        }
+        s->req = nullptr;
+        s->retiring = false;
+        srv->in_flight.fetch_sub(1);
+    }
+    // finished solves: status word of the slot's current generation
+    for (int i = 0; i < ns; ++i) {
+        Slot* s = c->slots[i].get();
+        if (!s->req || s->retiring) continue;
+        const int* hs = c->h_status + 4 * i;
+        if (!__atomic_load_n(hs, __ATOMIC_ACQUIRE) || __atomic_load_n(hs + 2, __ATOMIC_RELAXED) != s->gen) continue;
+        Request* q = s->req;
+        const int status = __atomic_load_n(hs + 1, __ATOMIC_RELAXED);
+        const bool ok = status == FFTCG_OK || status == FFTCG_ENOCONV;
+        if (ok && q->steps > 0) {
+            // the load step of this solve, on the device
+            launch_loadstep(s->x, s->t, s->d, (int)q->n, s->ws->ls_pv, s->ws->ls_pi, s->broken + s->step,
+                            c->stream);
+            if (s->step + 1 < q->steps) {
+                q->step_iters.push_back(__atomic_load_n(hs + 3, __ATOMIC_RELAXED));
+                s->step += 1;
+                start_solve(c, i);  // warm start: x stays in place
+                continue;
+            }
+        }
+        // retire: deactivate, copy results; finished when the copies land
+        c->h_table[i].active = 0;
+        upload_entry(c, i);
+        (void)hipMemcpyAsync(s->pin_state, s->ws->st, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream);
+        if (ok) {
+            (void)hipMemcpyAsync(q->pin_x, s->x, q->n * 8, hipMemcpyDeviceToHost, c->stream);
+            if (q->steps > 0)
+                (void)hipMemcpyAsync(q->pin_broken, s->broken, sizeof(int) * q->steps, hipMemcpyDeviceToHost,
+                                     c->stream);
+        }
+        (void)hipEventRecord(s->ev_retire, c->stream);
+        s->retiring = true;
+    }
+    // admissions (FIFO)
+    for (;;) {
+        Request* q = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (c->pending.empty()) break;
+            q = c->pending.front();
+        }
+        int idx = -1;
+        for (int i = 0; i < (int)c->slots.size(); ++i)
+            if (!c->slots[i]->req) {
+                idx = i;
+                break;
+            }
+        if (idx < 0) {
+            if (!add_slot(srv, c)) break;
+            idx = (int)c->slots.size() - 1;
+        }
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            c->pending.pop_front();
+            srv->queued -= 1;
+            srv->stats.admitted += 1;
+        }
+        srv->in_flight.fetch_add(1);
+        admit(c, q, idx);
+    }
+    // one chunk over all slots of the class when any solve is running
+    bool active = false;
+    for (auto& s : c->slots)
+        if (s->req && !s->retiring) active = true;
+    if (active && c->inflight < 2) {
+        const EngineOps* ops = c->plan->ops;
+        const int nsl = (int)c->slots.size();
+        for (int k = 0; k < srv->opts.chunk_iters; ++k)
+            ops->iter(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+        ops->check(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+        (void)hipEventRecord(c->ev[c->next_ev], c->stream);
+        c->next_ev ^= 1;
+        c->inflight += 1;
+    }
+    bool busy = active || c->inflight > 0;
+    for (auto& s : c->slots)
+        if (s->retiring) busy = true;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    return busy || !c->pending.empty();
+}
+
+void scheduler(fftcg_server_s* srv) {
+    (void)hipSetDevice(srv->opts.device);
+    while (!srv->stop.load()) {
+        std::vector<Class*> cls;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            for (auto& kv : srv->classes) cls.push_back(kv.second.get());
+        }
+        bool busy = false;
+        for (Class* c : cls) busy |= progress(srv, c);
+        if (!busy) {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            if (srv->queued == 0 && !srv->stop.load()) srv->cv.wait_for(lk, std::chrono::milliseconds(2));
+        } else {
+            std::this_thread::yield();
+        }
+    }
+}
+
+bool all_finite(const double* a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!isfinite(a[i])) return false;
+    return true;
+}
+
+void free_request_buffers(Request* q) {
+    if (q->pin_in) (void)hipHostFree(q->pin_in);
+    if (q->pin_x) (void)hipHostFree(q->pin_x);
+    if (q->pin_broken) (void)hipHostFree(q->pin_broken);
+    q->pin_in = q->pin_x = nullptr;
+    q->pin_broken = nullptr;
+}
+
+}  // namespace
+
+extern "C" int fftcg_server_create(const fftcg_server_opts* opts, fftcg_server_t* out) {
+    if (!opts || !out) return FFTCG_EINVAL;
+    if (opts->memory_budget == 0 || opts->max_slots < 0 || opts->chunk_iters < 0 || opts->refresh_period < 0 ||
+        opts->queue_cap < 0)
+        return FFTCG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opts->device < 0 || opts->device >= ndev) return FFTCG_EDEVICE;
+    fftcg_server_s* s = new (std::nothrow) fftcg_server_s();
+    if (!s) return FFTCG_ENOMEM;
+    s->opts = *opts;
+    if (s->opts.max_slots == 0) s->opts.max_slots = 64;
+    if (s->opts.chunk_iters == 0) s->opts.chunk_iters = 10;
+    if (s->opts.refresh_period == 0) s->opts.refresh_period = 50;
+    if (s->opts.queue_cap == 0) s->opts.queue_cap = 1 << 20;
+    s->thread = std::thread(scheduler, s);
+    *out = s;
+    return FFTCG_OK;
+}
+
+static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, const double* d, const double* b,
+                         const double* x0, const double* t, double tol, int maxit, int steps, uint64_t* ticket) {
+    if (!srv || !plan || !d || !b || !ticket) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    if (!(tol > 0.0) || !(tol < 1.0) || maxit < 1) return FFTCG_EINVAL;
+    if (!plan->ops) return FFTCG_EINVAL;
+    if (slot_footprint(plan) > srv->opts.memory_budget) return FFTCG_ENOMEM;
+    const size_t n = (size_t)plan->L * plan->L;
+    for (size_t i = 0; i < n; ++i)
+        if (!(d[i] >= 0.0) || !isfinite(d[i])) return FFTCG_EINVAL;
+    if (!all_finite(b, n) || (x0 && !all_finite(x0, n))) return FFTCG_EINVAL;
+    if (t)
+        for (size_t i = 0; i < n; ++i)
+            if (!(t[i] > 0.0) || !isfinite(t[i])) return FFTCG_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->queued >= srv->opts.queue_cap) return FFTCG_EAGAIN;
+    }
+    std::unique_ptr<Request> q(new (std::nothrow) Request());
+    if (!q) return FFTCG_ENOMEM;
+    q->plan = plan;
+    q->precision = precision;
+    q->tol = tol;
+    q->maxit = maxit;
+    q->steps = steps;
+    q->n = n;
+    q->has_x0 = x0 != nullptr;
+    bool ok = hipHostMalloc((void**)&q->pin_in, n * 8 * 4, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&q->pin_x, n * 8, hipHostMallocDefault) == hipSuccess &&
+              (steps == 0 ||
+               hipHostMalloc((void**)&q->pin_broken, sizeof(int) * steps, hipHostMallocDefault) == hipSuccess);
+    if (!ok) {
+        free_request_buffers(q.get());
+        return FFTCG_ENOMEM;
+    }
+    memcpy(q->pin_in, d, n * 8);
+    memcpy(q->pin_in + n, b, n * 8);
+    if (x0) memcpy(q->pin_in + 2 * n, x0, n * 8);
+    if (t) memcpy(q->pin_in + 3 * n, t, n * 8);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->queued >= srv->opts.queue_cap) {
+        free_request_buffers(q.get());
+        return FFTCG_EAGAIN;
+    }
+    Class* c = nullptr;
+    auto it = srv->classes.find({plan, precision});
+    if (it == srv->classes.end()) {
+        const int rc = make_class(srv, plan, precision, &c);
+        if (rc != FFTCG_OK) {
+            free_request_buffers(q.get());
+            return rc;
+        }
+    } else {
+        c = it->second.get();
+    }
+    q->ticket = srv->next_ticket++;
+    *ticket = q->ticket;
+    plan->refs.fetch_add(1);
+    c->pending.push_back(q.get());
+    srv->queued += 1;
+    srv->stats.submitted += 1;
+    srv->requests[q->ticket] = std::move(q);
+    srv->cv.notify_all();
+    return FFTCG_OK;
+}
+
+extern "C" int fftcg_submit(fftcg_server_t srv, fftcg_plan_t plan, int precision, const double* d, const double* b,
+                            const double* x0, double tol, int maxit, uint64_t* ticket) {
+    return submit_common(srv, plan, precision, d, b, x0, nullptr, tol, maxit, 0, ticket);
+}
+
+extern "C" int fftcg_submit_sequence(fftcg_server_t srv, fftcg_plan_t plan, int precision, const double* d,
+                                     const double* b, const double* t, double tol, int maxit, int steps,
+                                     uint64_t* ticket) {
+    if (!t || steps < 1 || steps > kMaxSteps) return FFTCG_EINVAL;
+    return submit_common(srv, plan, precision, d, b, nullptr, t, tol, maxit, steps, ticket);
+}
+
+static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
+                       fftcg_info* info, bool seq) {
+    if (!srv) return FFTCG_EINVAL;
+    std::unique_ptr<Request> q;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->requests.find(ticket);
+        if (it == srv->requests.end()) return FFTCG_ENOTFOUND;
+        if (seq != (it->second->steps > 0)) return FFTCG_EINVAL;
+        if (!it->second->done) return FFTCG_PENDING;
+        q = std::move(it->second);
+        srv->requests.erase(it);
+    }
+    const int st = q->status;
+    if (st == FFTCG_OK || st == FFTCG_ENOCONV) {
+        if (x) memcpy(x, q->pin_x, q->n * 8);
+        if (seq && broken) memcpy(broken, q->pin_broken, sizeof(int) * q->steps);
+        if (seq && step_iters)
+            for (int i = 0; i < q->steps; ++i) step_iters[i] = i < (int)q->step_iters.size() ? q->step_iters[i] : -1;
+    }
+    if (info) *info = q->info;
+    free_request_buffers(q.get());
+    return st;
+}
+
+extern "C" int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info) {
+    return poll_common(srv, ticket, x, nullptr, nullptr, info, false);
+}
+
+extern "C" int fftcg_poll_sequence(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
+                                   fftcg_info* info) {
+    return poll_common(srv, ticket, x, broken, step_iters, info, true);
+}
+
+extern "C" int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out) {
+    if (!srv || !out) return FFTCG_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->stats;
+    out->bytes_in_use = srv->bytes_in_use.load();
+    out->queued = srv->queued;
+    out->in_flight = srv->in_flight.load();
+    return FFTCG_OK;
+}
+
+extern "C" int fftcg_server_destroy(fftcg_server_t srv) {
+    if (!srv) return FFTCG_EINVAL;
+    srv->stop.store(true);
+    srv->cv.notify_all();
+    if (srv->thread.joinable()) srv->thread.join();
+    for (auto& kv : srv->classes) destroy_class(kv.second.get());
+    for (auto& kv : srv->requests) {
+        Request* q = kv.second.get();
+        if (!q->done) q->plan->refs.fetch_sub(1);
+        free_request_buffers(q);
+    }
+    delete srv;
+    return FFTCG_OK;
+}

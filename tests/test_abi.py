@@ -96,3 +96,25 @@ def test_null_plan_calls(lib):
     assert lib.fftcg_plan_info(None, None, None, None, None) == binding.EINVAL
     idx = ctypes.c_int()
     assert lib.fftcg_loadstep(None, P(1), P(2), P(3), ctypes.byref(idx), None) == binding.EINVAL
+
+
+def test_server_calls_without_server(lib):
+    P = ctypes.c_void_p
+    tk = ctypes.c_uint64()
+    assert lib.fftcg_server_create(None, None) == binding.EINVAL
+    assert lib.fftcg_submit(None, None, 0, P(1), P(2), None, 1e-8, 10, ctypes.byref(tk)) == binding.EINVAL
+    assert lib.fftcg_poll(None, 1, None, None) == binding.EINVAL
+    assert lib.fftcg_server_destroy(None) == binding.EINVAL
+    assert lib.fftcg_server_get_stats(None, None) == binding.EINVAL
+    o = binding.ServerOpts(0, 0, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert lib.fftcg_server_create(ctypes.byref(o), ctypes.byref(h)) == binding.EINVAL   # zero budget
+
+
+def test_server_create_without_gpu(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    o = binding.ServerOpts(1 << 30, 0, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert lib.fftcg_server_create(ctypes.byref(o), ctypes.byref(h)) == binding.EDEVICE

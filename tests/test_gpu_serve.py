@@ -1,0 +1,203 @@
+"""The continuous-batching server on the GPU.
+
+* every request's x is bitwise the same alone and in a mix of sizes, and
+  within 1e-8 of the oracle;
+* admission under a tight memory budget (requests wait for slots) and the
+  error paths: ENOMEM, EAGAIN, ENOTFOUND;
+* a request that fails (maxit reached) retires alone while the others in its
+  batch are unchanged;
+* a load-stepped sequence: each broken index is a valid choice for the
+  oracle's solution of that step (near-ties admit several answers), the
+  oracle replays the GPU's choices, and the final x matches it.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from paper_1305_3625_amd import binding
+from workloads import spectrum, padded_instance, c4_request, c5_sequence
+from oracle import (kernel_table, reference_solve, apply_direct, loadstep_argmax, loadstep_valid,
+                    lambda_lb)
+from gpu_util import banner, relerr
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-3
+
+
+def _wait(srv, tickets, L, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for tk in tickets:
+            if tk in out:
+                continue
+            r = srv.poll(tk, L[tk] if isinstance(L, dict) else L)
+            if r.status != binding.PENDING:
+                out[tk] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(tickets) - len(out)} requests still pending")
+        time.sleep(0.001)
+    return out
+
+
+@pytest.fixture(scope="module")
+def plans():
+    return {M: binding.Plan(M // 2, 1, spectrum(M, EPS)) for M in (32, 64, 128, 256)}
+
+
+def test_alone_equals_mix(plans):
+    banner("serve-alone-vs-mix")
+    reqs = [c4_request(k, M) for k, M in enumerate([64, 128, 64, 256, 32, 128, 64, 256])]
+    srv = binding.Server(memory_budget=1 << 30)
+    alone = []
+    for r in reqs:
+        st, tk = srv.submit(plans[r["M"]], r["d"], r["b"], tol=1e-8)
+        assert st == binding.OK
+        res = _wait(srv, [tk], r["L"])[tk]
+        assert res.status == binding.OK, res.info
+        alone.append(res.x)
+    # all at once, twice (the second batch sees slots reused)
+    for _ in range(2):
+        tks = []
+        Ls = {}
+        for r in reqs:
+            st, tk = srv.submit(plans[r["M"]], r["d"], r["b"], tol=1e-8)
+            assert st == binding.OK
+            tks.append(tk)
+            Ls[tk] = r["L"]
+        res = _wait(srv, tks, Ls)
+        for r, tk, xa in zip(reqs, tks, alone):
+            assert res[tk].status == binding.OK
+            assert np.array_equal(res[tk].x, xa)
+    stats = srv.stats()
+    assert stats["completed"] == 3 * len(reqs) and stats["failed"] == 0
+    srv.close()
+    # accuracy against the oracle
+    for r, xa in zip(reqs[:4], alone[:4]):
+        xr, info = reference_solve(spectrum(r["M"], EPS), r["d"], r["b"], 1)
+        assert relerr(xa, xr) <= 1e-8
+
+
+def test_tight_budget_admission(plans):
+    banner("serve-tight-budget")
+    probe = binding.Server(memory_budget=1 << 30)
+    r = c4_request(100, 256)
+    st, tk = probe.submit(plans[256], r["d"], r["b"])
+    _wait(probe, [tk], 128)
+    one = probe.stats()["bytes_in_use"]
+    probe.close()
+    assert one > 0
+    srv = binding.Server(memory_budget=int(2.5 * one))
+    reqs = [c4_request(200 + k, 256) for k in range(6)]
+    tks = []
+    for r in reqs:
+        st, tk = srv.submit(plans[256], r["d"], r["b"])
+        assert st == binding.OK
+        tks.append(tk)
+    peak = 0
+    t0 = time.time()
+    done = {}
+    while len(done) < len(tks) and time.time() - t0 < 120:
+        peak = max(peak, srv.stats()["in_flight"])
+        assert srv.stats()["bytes_in_use"] <= int(2.5 * one)
+        for tk in tks:
+            if tk not in done:
+                res = srv.poll(tk, 128)
+                if res.status != binding.PENDING:
+                    done[tk] = res
+        time.sleep(0.0005)
+    assert len(done) == len(tks)
+    assert all(v.status == binding.OK for v in done.values())
+    assert peak <= 2
+    srv.close()
+
+
+def test_error_paths(plans):
+    banner("serve-errors")
+    r = c4_request(300, 256)
+    srv = binding.Server(memory_budget=1 << 20)   # less than one slot of M=256
+    st, _ = srv.submit(plans[256], r["d"], r["b"])
+    assert st == binding.ENOMEM
+    bad = r["b"].copy()
+    bad[0, 0] = np.nan
+    st, _ = srv.submit(plans[32], np.ones((16, 16)), bad[:16, :16])
+    assert st == binding.EINVAL
+    res = srv.poll(123456, 16)
+    assert res.status == binding.ENOTFOUND
+    srv.close()
+    # queue cap: with one slot and a queue of one, a burst gets EAGAIN
+    srv = binding.Server(memory_budget=1 << 30, max_slots=1, queue_cap=1)
+    r = c4_request(301, 256)
+    sts, tks = [], []
+    for _ in range(40):
+        st, tk = srv.submit(plans[256], r["d"], r["b"])
+        sts.append(st)
+        if st == binding.OK:
+            tks.append(tk)
+    assert binding.EAGAIN in sts
+    res = _wait(srv, tks, 128)
+    assert all(v.status == binding.OK for v in res.values())
+    tk = tks[0]
+    assert srv.poll(tk, 128).status == binding.ENOTFOUND
+    srv.close()
+
+
+def test_failed_request_is_isolated(plans):
+    banner("serve-isolation")
+    reqs = [c4_request(400 + k, 128) for k in range(4)]
+    srv = binding.Server(memory_budget=1 << 30)
+    alone = []
+    for r in reqs:
+        st, tk = srv.submit(plans[128], r["d"], r["b"])
+        alone.append(_wait(srv, [tk], 64)[tk].x)
+    tks = []
+    for i, r in enumerate(reqs):
+        st, tk = srv.submit(plans[128], r["d"], r["b"], maxit=(2 if i == 1 else 10000))
+        tks.append(tk)
+    res = _wait(srv, tks, 64)
+    assert res[tks[1]].status == binding.ENOCONV
+    assert res[tks[1]].info["iterations"] == 2
+    for i in (0, 2, 3):
+        assert res[tks[i]].status == binding.OK
+        assert np.array_equal(res[tks[i]].x, alone[i])
+    srv.close()
+
+
+def test_loadstep_sequence_replay():
+    L, steps = 32, 24
+    M = 2 * L
+    seq = c5_sequence(7, L=L)
+    gh = spectrum(M, EPS)
+    g = kernel_table(gh)
+    plan = binding.Plan(L, 1, gh)
+    srv = binding.Server(memory_budget=1 << 30)
+    banner("serve-sequence", L, steps)
+    st, tk = srv.submit_sequence(plan, seq["d"], seq["b"], seq["t"], steps, tol=1e-8)
+    assert st == binding.OK
+    t0 = time.time()
+    while True:
+        r = srv.poll_sequence(tk, L, steps)
+        if r.status != binding.PENDING:
+            break
+        assert time.time() - t0 < 120
+        time.sleep(0.002)
+    assert r.status == binding.OK, r.info
+    x_gpu, broken, iters = r.x
+    assert len(set(broken.tolist())) == steps and np.all(broken >= 0)
+    # replay: the oracle solves each step with the GPU's sequence of breaks
+    d = seq["d"].copy()
+    x_ref = None
+    for s in range(steps):
+        x_ref, info = reference_solve(gh, d, seq["b"], 1, g=g)
+        # the GPU's solution of this step has certified error <= 1e-8 (relative,
+        # 2-norm), which bounds its max-norm error
+        e_inf = 1e-8 * np.linalg.norm(x_ref) / (1 - 1e-8) + info["bound"] * np.linalg.norm(x_ref)
+        j = int(broken[s])
+        assert loadstep_valid(j, x_ref, seq["t"], d, e_inf), (s, j, loadstep_argmax(x_ref, seq["t"], d))
+        d.ravel()[j] = 0.0
+    # the returned x is the last step's solution (before its own break)
+    assert relerr(x_gpu, x_ref) <= 1e-8
+    srv.close()
