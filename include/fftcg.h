@@ -64,10 +64,11 @@ extern "C" {
 #define FFTCG_MIXED 1
 
 /* ---- engines (fftcg_plan_set_engine) -----------------------------------
- * AUTO     : fused single-workgroup engine for M <= 128, multi-pass above.
+ * AUTO     : fused single-workgroup engine for M <= 64, multi-pass above.
  * MULTIPASS: three HBM passes per product (row R2C, column FFT*ghat*IFFT,
- *            row C2R + epilogue); available for M >= 8.
- * FUSED    : one workgroup per solve, whole CG iteration in LDS; M <= 128.  */
+ *            row C2R + epilogue); every grid.
+ * FUSED    : one workgroup per solve, whole CG loop in one kernel with the
+ *            product in LDS; M <= 64.                                       */
 #define FFTCG_ENGINE_AUTO      0
 #define FFTCG_ENGINE_MULTIPASS 1
 #define FFTCG_ENGINE_FUSED     2

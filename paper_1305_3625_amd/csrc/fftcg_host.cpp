@@ -308,7 +308,7 @@ extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) {
 }
 
 int fftcg::plan_engine(const fftcg_plan_s* p) {
-    if (p->engine == FFTCG_ENGINE_AUTO) return (p->M <= 128 && p->fused_ok) ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
+    if (p->engine == FFTCG_ENGINE_AUTO) return p->fused_ok ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
     return p->engine;
 }
 

@@ -46,7 +46,7 @@ struct Geo {
     static constexpr int ER = fft_elems(N);
     static constexpr int PR = N / ER;
     static constexpr int ROW_WORDS = LdsLay<T, 1, 4, 1>::words(N);
-    static constexpr int ROW_LDS_CAP = 65536 / (int)sizeof(cx<T>);
+    static constexpr int ROW_LDS_CAP = 73728 / (int)sizeof(cx<T>);  // two workgroups per CU
     static constexpr int RPW0 = cmin(L, cmax(1, 256 / PR));
     static constexpr int RPW_fit(int r) { return (r > 1 && r * ROW_WORDS > ROW_LDS_CAP) ? RPW_fit(r / 2) : r; }
     static constexpr int RPW = RPW_fit(RPW0);
@@ -85,6 +85,102 @@ __device__ __forceinline__ void publish_status(const SlotDesc& sd, int done, int
     __hip_atomic_store(sd.host_status + 2, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(sd.host_status + 3, iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(sd.host_status, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// ---- CG control shared by both engines --------------------------------------
+
+// Whether an FP64 check must come before the next iteration, given the
+// recursive r.r: at maxit; every `refresh` iterations (mixed mode); when the
+// recursive residual meets the stop rule; or, as a reliable update, once it
+// has fallen by sqrt(delta2) since the last replacement (past that point the
+// working-precision recursion may drift from the true residual).  The last
+// two need an iteration since the previous check, so checks alternate with
+// progress.
+__device__ __forceinline__ bool check_due(const SolveState* st, double rr) {
+    const int iters = st->iters;
+    const bool progressed = iters > st->last_check_iter;
+    const bool periodic = st->refresh > 0 && iters - st->last_check_iter >= st->refresh;
+    const bool candidate = progressed && !(rr > st->trigger_rr);
+    const bool reliable = progressed && rr <= st->delta2 * st->rho_ref;
+    return iters >= st->maxit || candidate || periodic || reliable;
+}
+
+// Outcome of an FP64 check from its reductions: |b - A x|^2 (R), |x|^2 (X),
+// |b|^2 (B), |r_working|^2 (RW), invalid-input count (BAD), drift of the
+// recursive residual (DIFF), min d.  Updates the state (one thread); returns
+// 1 when CG continues with the replaced residual (r.r = RW), 0 when done.
+__device__ inline int check_decide(SolveState* st, double R, double X, double B, double RW, double BAD,
+                                   double DIFF, double dmin) {
+    const bool first = st->checks == 0;
+    st->checks += 1;
+    if (first) {
+        st->bnorm = sqrt(B);
+        st->lam_lb = dmin + st->gmin;
+    }
+    const double rt = sqrt(R), xn = sqrt(X), bn = st->bnorm;
+    if (first && BAD > 0.0) {
+        st->status = ST_EINVAL;
+        st->done = 1;
+        return 0;
+    }
+    if (first && bn == 0.0) {
+        st->status = ST_OK;
+        st->done = 1;
+        st->bzero = 1;
+        st->true_relres = 0.0;
+        st->bound = 0.0;
+        return 0;
+    }
+    if (!isfinite(rt) || !isfinite(xn)) {
+        st->status = ST_EBREAKDOWN;
+        st->done = 1;
+        return 0;
+    }
+    const double tau = st->tau, lam = st->lam_lb;
+    const bool lit = rt <= st->tol * bn;
+    const double cert_target = tau * lam * xn / (1.0 + tau);
+    const bool cert = rt <= cert_target;
+    const double e = rt / lam;
+    st->true_relres = rt / bn;
+    st->bound = xn > e ? e / (xn - e) : 1.0e300;
+    if (lit && st->iters_literal < 0) st->iters_literal = st->iters;
+    if (lit && cert) {
+        st->status = ST_OK;
+        st->done = 1;
+        return 0;
+    }
+    if (st->iters >= st->maxit) {
+        st->status = ST_ENOCONV;
+        st->done = 1;
+        return 0;
+    }
+    double trig = st->tol * bn;
+    if (xn > 0.0 && cert_target < trig) trig = cert_target;
+    st->trigger_rr = trig * trig;
+    if (first) {
+        st->worse = 0;
+        st->best_rt = rt;
+    } else if (rt >= st->best_rt) {
+        st->worse += 1;
+    } else {
+        st->worse = 0;
+        st->best_rt = rt;
+    }
+    if (st->worse >= 2) {
+        st->restart = 1;
+        st->worse = 0;
+    }
+    // Keeping p after the replacement is sound only while the recursive
+    // residual still tracked the true one; past 10% drift the old direction
+    // is no longer conjugate, so restart.
+    if (!first && !(DIFF <= 0.01 * R)) st->restart = 1;
+    st->rho_ref = RW;
+    st->alpha = 0.0;
+    st->last_check_iter = st->iters;
+    st->last_rt = rt;
+    st->xnorm = xn;
+    st->pause = 0;
+    return 1;
 }
 
 // ---- slot access policies -------------------------------------------------
@@ -176,20 +272,7 @@ struct ProCG {
         if (!GateIter::ok(sd)) return false;
         SolveState* st = sd.st;
         const double rr = sum_partials<NT>(sd.part + PS_RR * stride, npart_rr, sh.red);
-        const int iters = st->iters;
-        // a check is due at maxit, every `refresh` iterations (mixed mode), or
-        // when the recursive residual meets the stop rule; the last needs at
-        // least one iteration since the previous check so checks always
-        // alternate with progress
-        const bool progressed = iters > st->last_check_iter;
-        const bool periodic = st->refresh > 0 && iters - st->last_check_iter >= st->refresh;
-        const bool candidate = progressed && !(rr > st->trigger_rr);
-        // reliable update: the recursive residual fell by sqrt(delta2) since the
-        // last replacement, the point after which it may drift from the true
-        // one by more than the working precision can carry
-        const bool reliable = progressed && rr <= st->delta2 * st->rho_ref;
-        const bool pause = iters >= st->maxit || candidate || periodic || reliable;
-        if (pause) {
+        if (check_due(st, rr)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) st->pause = 1;
             return false;
         }
@@ -633,72 +716,7 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
     for (int i = threadIdx.x; i < npart_chk; i += NT) dmin = fmin(dmin, part[PS_CHK_DMIN * stride + i]);
     dmin = block_min<NT>(dmin, red);
     if (threadIdx.x == 0) {
-        int update = 0;
-        const bool first = st->checks == 0;
-        st->checks += 1;
-        if (first) {
-            st->bnorm = sqrt(B);
-            st->lam_lb = dmin + st->gmin;
-        }
-        const double rt = sqrt(R), xn = sqrt(X), bn = st->bnorm;
-        if (first && BAD > 0.0) {
-            st->status = ST_EINVAL;
-            st->done = 1;
-        } else if (first && bn == 0.0) {
-            st->status = ST_OK;
-            st->done = 1;
-            st->bzero = 1;
-            st->true_relres = 0.0;
-            st->bound = 0.0;
-        } else if (!isfinite(rt) || !isfinite(xn)) {
-            st->status = ST_EBREAKDOWN;
-            st->done = 1;
-        } else {
-            const double tau = st->tau, lam = st->lam_lb;
-            const bool lit = rt <= st->tol * bn;
-            const double cert_target = tau * lam * xn / (1.0 + tau);
-            const bool cert = rt <= cert_target;
-            const double e = rt / lam;
-            st->true_relres = rt / bn;
-            st->bound = xn > e ? e / (xn - e) : 1.0e300;
-            if (lit && st->iters_literal < 0) st->iters_literal = st->iters;
-            if (lit && cert) {
-                st->status = ST_OK;
-                st->done = 1;
-            } else if (st->iters >= st->maxit) {
-                st->status = ST_ENOCONV;
-                st->done = 1;
-            } else {
-                double trig = st->tol * bn;
-                if (xn > 0.0 && cert_target < trig) trig = cert_target;
-                st->trigger_rr = trig * trig;
-                if (first) {
-                    st->worse = 0;
-                    st->best_rt = rt;
-                } else if (rt >= st->best_rt) {
-                    st->worse += 1;
-                } else {
-                    st->worse = 0;
-                    st->best_rt = rt;
-                }
-                if (st->worse >= 2) {
-                    st->restart = 1;
-                    st->worse = 0;
-                }
-                // Keeping p after the replacement is sound only while the
-                // recursive residual still tracked the true one; past 10%
-                // drift the old direction is no longer conjugate, so restart.
-                if (!first && !(DIFF <= 0.01 * R)) st->restart = 1;
-                st->rho_ref = RW;
-                st->alpha = 0.0;
-                st->last_check_iter = st->iters;
-                st->last_rt = rt;
-                st->xnorm = xn;
-                st->pause = 0;
-                update = 1;
-            }
-        }
-        s_update = update;
+        s_update = check_decide(st, R, X, B, RW, BAD, DIFF, dmin);
         publish_status(sd, st->done, st->status, st->gen, st->iters);
     }
     __syncthreads();

@@ -16,5 +16,9 @@ void fused_free(fftcg_plan_s* p);
 int fused_apply(fftcg_plan_s* p, int precision, const double* d, const double* x, double* y, hipStream_t s);
 int fused_solve(fftcg_plan_s* p, int precision, const double* d, const double* b, const double* x0, double tol,
                 int maxit, double* x, fftcg_info* info, hipStream_t s);
+// Runs up to max_iters CG iterations (plus the checks they need) for every
+// slot of the table, one workgroup per slot.
+void fused_launch(const fftcg_plan_s* p, int precision, const SlotDesc* slots, int nslots, int max_iters,
+                  hipStream_t s);
 
 }  // namespace fftcg

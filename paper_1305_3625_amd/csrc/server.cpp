@@ -39,6 +39,7 @@
 #include "engine.hpp"
 #include "fftcg.h"
 #include "fftcg_internal.hpp"
+#include "fused.hpp"
 
 using namespace fftcg;
 
@@ -376,11 +377,16 @@ bool progress(fftcg_server_s* srv, Class* c) {
     for (auto& s : c->slots)
         if (s->req && !s->retiring) active = true;
     if (active && c->inflight < 2) {
-        const EngineOps* ops = c->plan->ops;
         const int nsl = (int)c->slots.size();
-        for (int k = 0; k < srv->opts.chunk_iters; ++k)
-            ops->iter(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
-        ops->check(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+        if (plan_engine(c->plan) == FFTCG_ENGINE_FUSED) {
+            // one workgroup per slot runs the chunk's iterations and checks
+            fused_launch(c->plan, c->precision, c->d_table, nsl, srv->opts.chunk_iters, c->stream);
+        } else {
+            const EngineOps* ops = c->plan->ops;
+            for (int k = 0; k < srv->opts.chunk_iters; ++k)
+                ops->iter(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+            ops->check(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+        }
         (void)hipEventRecord(c->ev[c->next_ev], c->stream);
         c->next_ev ^= 1;
         c->inflight += 1;

@@ -25,9 +25,11 @@ def _inputs(L, padded, seed):
 
 
 @pytest.mark.parametrize("L,padded", SMALL)
-@pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS])
+@pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS, binding.ENGINE_FUSED])
 def test_apply_small_direct(L, padded, engine):
     M = 2 * L if padded else L
+    if engine == binding.ENGINE_FUSED and M > 64:
+        pytest.skip("the fused engine serves M <= 64")
     eps = 1e-3
     gh = spectrum(M, eps)
     g = kernel_table(gh)

@@ -50,14 +50,15 @@ def test_closed_form():
 @pytest.mark.parametrize("L", [2, 4, 8, 16])
 @pytest.mark.parametrize("padded", [0, 1])
 @pytest.mark.parametrize("mode", MODES)
-def test_cholesky(L, padded, mode):
+@pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS, binding.ENGINE_FUSED])
+def test_cholesky(L, padded, mode, engine):
     prec, tol, bar = mode
     inst = padded_instance(L, [60, L], eps=1e-3) if padded else periodic_instance(L, [61, L], eps=1e-2)
     g = kernel_table(inst["ghat"])
     xs = solve_dense(g, inst["d"], inst["b"], padded)
     plan = binding.Plan(L, padded, inst["ghat"])
-    plan.set_engine(binding.ENGINE_MULTIPASS)
-    banner("cholesky", L, padded, prec)
+    plan.set_engine(engine)
+    banner("cholesky", L, padded, prec, engine)
     x, info = _solve(plan, inst, prec, tol)
     assert info["status"] == binding.OK, info
     err = relerr(x, xs)
@@ -66,17 +67,19 @@ def test_cholesky(L, padded, mode):
 
 
 @pytest.mark.parametrize("s", [0, 1, 2, 3])
-def test_periodic_L64(s):
+@pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS, binding.ENGINE_FUSED])
+def test_periodic_L64(s, engine):
     inst = c1_instance(s)
     xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 0)
     assert rinfo["bound"] < 1e-12
     plan = binding.Plan(64, 0, inst["ghat"])
-    plan.set_engine(binding.ENGINE_MULTIPASS)
-    banner("periodic-L64", s)
+    plan.set_engine(engine)
+    banner("periodic-L64", s, engine)
     x, info = _solve(plan, inst, binding.FP64, inst["tol"])
     assert info["status"] == binding.OK
     err = relerr(x, xr)
-    print(f"seed {s}: iters {info['iterations']} err {err:.3e} bound {info['error_bound']:.3e}")
+    print(f"seed {s} engine {engine}: iters {info['iterations']} err {err:.3e} bound {info['error_bound']:.3e} "
+          f"ms {info['device_ms']:.3f}")
     assert err <= 1e-10
     assert info["error_bound"] <= 1e-10
 
