@@ -50,34 +50,34 @@ def _run(cmd):
     return out
 
 
-def _obj(name):
-    return os.path.join(BUILD, name + ".o")
-
-
-def _jobs():
+def _jobs(build_dir, extra):
+    obj = lambda name: os.path.join(build_dir, name + ".o")  # noqa: E731
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         lang = ["-x", "hip"] if s.endswith(".cpp") else []
-        yield [HIPCC, *CXXFLAGS, *lang, "-c", src, "-o", _obj(os.path.splitext(s)[0])]
+        yield [HIPCC, *CXXFLAGS, *extra, *lang, "-c", src, "-o", obj(os.path.splitext(s)[0])]
     for m, pad in ENGINE_SIZES:
-        yield [HIPCC, *CXXFLAGS, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", "-c",
-               os.path.join(CSRC, "engine_inst.hip"), "-o", _obj(f"engine_{m}_{pad}")]
+        yield [HIPCC, *CXXFLAGS, *extra, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", "-c",
+               os.path.join(CSRC, "engine_inst.hip"), "-o", obj(f"engine_{m}_{pad}")]
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, extra_flags=(), lib_path: str = LIB,
+          build_dir: str = BUILD) -> str:
+    """Compiles every source (always) and links lib_path.  extra_flags are
+    passed to every compile (e.g. -D switches of tuning variants)."""
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
-    cmds = list(_jobs())
+    cmds = list(_jobs(build_dir, list(extra_flags)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, cmds):
             if verbose and out.strip():
                 print(out)
     objs = [c[-1] for c in cmds]
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-fPIC", "-o", tmp,
           *objs, "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 def main(argv=None):

@@ -117,19 +117,24 @@ __device__ __forceinline__ void dft(cx<T>* v) {
 }
 
 // ---- radix plans ----------------------------------------------------------
-// Forward order: 16, 16, ..., then the remainder radix (2, 4 or 8).
-// Reversed order: remainder first.  Lengths below 16 use one stage.
-__host__ __device__ constexpr int fft_elems(int N) { return N >= 16 ? 16 : N; }
+// Forward order: MAXR, MAXR, ..., then the remainder radix.  Reversed order:
+// remainder first.  Lengths below MAXR use one stage.  MAXR = 16 by default.
+#ifndef FFTCG_MAXR
+#define FFTCG_MAXR 16
+#endif
+constexpr int MAXR = FFTCG_MAXR;
+constexpr int LGMAXR = MAXR == 16 ? 4 : (MAXR == 8 ? 3 : 2);
+__host__ __device__ constexpr int fft_elems(int N) { return N >= MAXR ? MAXR : N; }
 __host__ __device__ constexpr int fft_nstages(int N) {
-    return N <= 1 ? 0 : (N < 16 ? 1 : ilog2c(N) / 4 + (ilog2c(N) % 4 ? 1 : 0));
+    return N <= 1 ? 0 : (N < MAXR ? 1 : ilog2c(N) / LGMAXR + (ilog2c(N) % LGMAXR ? 1 : 0));
 }
 __host__ __device__ constexpr int fft_radix(int N, bool rev, int s) {
     // stage s of the plan
-    return N < 16 ? N
-                  : (ilog2c(N) % 4 == 0
-                         ? 16
-                         : (rev ? (s == 0 ? (1 << (ilog2c(N) % 4)) : 16)
-                                : (s == fft_nstages(N) - 1 ? (1 << (ilog2c(N) % 4)) : 16)));
+    return N < MAXR ? N
+                    : (ilog2c(N) % LGMAXR == 0
+                           ? MAXR
+                           : (rev ? (s == 0 ? (1 << (ilog2c(N) % LGMAXR)) : MAXR)
+                                  : (s == fft_nstages(N) - 1 ? (1 << (ilog2c(N) % LGMAXR)) : MAXR)));
 }
 __host__ __device__ constexpr int fft_ns(int N, bool rev, int s) {
     return s == 0 ? 1 : fft_ns(N, rev, s - 1) * fft_radix(N, rev, s - 1);
@@ -193,6 +198,16 @@ struct LdsLay {
 // other powers are products of at most three of them.
 template <typename T, int R, int DIR>
 __device__ __forceinline__ void twiddle_run(cx<T>* v, const cx<T>* __restrict__ tw, int m) {
+#ifdef FFTCG_TWIDDLE_DIRECT
+    // variant: one table read per power
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        cx<T> w = tw[r * m];
+        if (DIR > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+    }
+    return;
+#endif
     cx<T> p[16];
     p[1] = tw[m];
     if constexpr (R > 2) p[2] = tw[2 * m];

@@ -75,16 +75,16 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return (b & 7) * (G >> 3) + (b >> 3);
 }
 
-// Status words for the host (pinned, device-visible): [1] status, [2] the
-// solve's generation, then [0] done with release order, so a host that sees
-// done also sees the status and can tell a finished solve from an earlier
-// occupant of the same slot.
+// Status words for the host (pinned, device-visible): [1] status, [3]
+// iterations, then [0] = 2 * generation + done with release order.  Done and
+// the solve's generation travel in one word, so a host polling a reused slot
+// can never pair a stale done of the previous occupant with the new
+// generation; a host that sees done also sees the status.
 __device__ __forceinline__ void publish_status(const SlotDesc& sd, int done, int status, int gen, int iters) {
     if (!sd.host_status) return;
     __hip_atomic_store(sd.host_status + 1, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(sd.host_status + 2, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(sd.host_status + 3, iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(sd.host_status, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(sd.host_status, 2 * gen + (done ? 1 : 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ---- CG control shared by both engines --------------------------------------
@@ -645,6 +645,26 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
     const SlotDesc& sd = slot.get();
     if (!GateIter::ok(sd)) return;
     SolveState* st = sd.st;
+    constexpr int VW = sizeof(W) == 4 ? 4 : 2;
+    using V = typename std::conditional<sizeof(W) == 4, float4, double2>::type;
+    const int nv = n / VW;
+    const int per = (nv + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * per;
+    const int hi = lo + per < nv ? lo + per : nv;
+    V* r = reinterpret_cast<V*>(sd.r);
+    const V* q = reinterpret_cast<const V*>(sd.q);
+    // the first PF vectors of r and q are requested before the p.q reduction
+    // so its latency overlaps the HBM reads
+    constexpr int PF = 4;
+    V rp[PF], qp[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int i = lo + threadIdx.x + u * NT;
+        if (i < hi) {
+            rp[u] = r[i];
+            qp[u] = q[i];
+        }
+    }
     const double pq = sum_partials<NT>(sd.part + PS_PQ * stride, npart_pq, red);
     const double rho = st->rho_cur;
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
@@ -662,19 +682,9 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
         st->iters += 1;
         st->restart = 0;
     }
-    constexpr int VW = sizeof(W) == 4 ? 4 : 2;
-    using V = typename std::conditional<sizeof(W) == 4, float4, double2>::type;
-    const int nv = n / VW;
-    const int per = (nv + gridDim.x - 1) / gridDim.x;
-    const int lo = blockIdx.x * per;
-    const int hi = lo + per < nv ? lo + per : nv;
-    V* r = reinterpret_cast<V*>(sd.r);
-    const V* q = reinterpret_cast<const V*>(sd.q);
     const W a = (W)alpha;
     double acc = 0.0;
-    for (int i = lo + threadIdx.x; i < hi; i += NT) {
-        V rv = r[i];
-        const V qv = q[i];
+    auto upd = [&](V rv, const V qv) {
         if constexpr (VW == 4) {
             rv.x -= a * qv.x;
             rv.y -= a * qv.y;
@@ -686,8 +696,14 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
             rv.y -= a * qv.y;
             acc += rv.x * rv.x + rv.y * rv.y;
         }
-        r[i] = rv;
+        return rv;
+    };
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int i = lo + threadIdx.x + u * NT;
+        if (i < hi) r[i] = upd(rp[u], qp[u]);
     }
+    for (int i = lo + threadIdx.x + PF * NT; i < hi; i += NT) r[i] = upd(r[i], q[i]);
     const double s = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) sd.part[PS_RR * stride + blockIdx.x] = s;
 }

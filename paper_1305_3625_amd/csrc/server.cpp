@@ -317,7 +317,8 @@ bool progress(fftcg_server_s* srv, Class* c) {
         Slot* s = c->slots[i].get();
         if (!s->req || s->retiring) continue;
         const int* hs = c->h_status + 4 * i;
-        if (!__atomic_load_n(hs, __ATOMIC_ACQUIRE) || __atomic_load_n(hs + 2, __ATOMIC_RELAXED) != s->gen) continue;
+        // one word: 2 * generation + done (see publish_status)
+        if (__atomic_load_n(hs, __ATOMIC_ACQUIRE) != 2 * s->gen + 1) continue;
         Request* q = s->req;
         const int status = __atomic_load_n(hs + 1, __ATOMIC_RELAXED);
         const bool ok = status == FFTCG_OK || status == FFTCG_ENOCONV;
