@@ -123,6 +123,7 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
         for tk, L in tks:
             while srv.poll(tk, L).status == binding.PENDING:
                 time.sleep(0.0005)
+        srv.completed()  # drop the warm-up tickets
         outstanding = {}
         lat, iters, bad = [], [], 0
         t0 = time.perf_counter()
@@ -137,20 +138,18 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
                 else:
                     bad += 1
                 k += 1
-            done = []
-            for tk, (kk, L) in outstanding.items():
-                res = srv.poll(tk, L)
-                if res.status != binding.PENDING:
-                    t = time.perf_counter() - t0
-                    lat.append(t - arrivals[kk])
-                    iters.append(res.info["iterations"])
-                    if res.status != binding.OK:
-                        bad += 1
-                    done.append(tk)
+            done = srv.completed()
             for tk in done:
-                del outstanding[tk]
-            if not done and k < len(reqs):
-                time.sleep(max(0.0, min(2e-4, arrivals[k] - (time.perf_counter() - t0))))
+                kk, L = outstanding.pop(tk)
+                res = srv.poll(tk, L)
+                t = time.perf_counter() - t0
+                lat.append(t - arrivals[kk])
+                iters.append(res.info["iterations"])
+                if res.status != binding.OK:
+                    bad += 1
+            if not done:
+                nxt = arrivals[k] - (time.perf_counter() - t0) if k < len(reqs) else 2e-4
+                time.sleep(max(0.0, min(2e-4, nxt)))
         makespan = time.perf_counter() - t0
         stats = srv.stats()
         srv.close()

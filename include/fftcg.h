@@ -215,6 +215,15 @@ int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info)
 int fftcg_poll_sequence(fftcg_server_t srv, uint64_t ticket, double* x,
                         int* broken, int* step_iters, fftcg_info* info);
 
+/* fftcg_server_completed -- tickets whose requests finished since the last
+ * call, in completion order, so a client polls only those.
+ *   out   HOST array of cap entries; n receives the number written.
+ * Each ticket is reported once; fftcg_poll then returns its result.  The
+ * server keeps the 2^20 most recent unreported tickets (older ones are
+ * dropped, their results stay pollable).  FFTCG_EINVAL on NULL srv/n, cap<0
+ * or NULL out with cap>0.                                                  */
+int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap, int* n);
+
 /* Counters of the server (host pointer).                                   */
 int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out);
 

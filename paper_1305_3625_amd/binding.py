@@ -30,7 +30,7 @@ EXPORTS = [
     "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_info",
     "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
-    "fftcg_poll_sequence", "fftcg_server_get_stats", "fftcg_server_destroy",
+    "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_destroy",
     "fftcg_strerror", "fftcg_version",
 ]
 
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
         "fftcg_submit_sequence": (I, [P, P, I, P, P, P, D, I, I, U64P]),
         "fftcg_poll": (I, [P, ctypes.c_uint64, P, ctypes.POINTER(Info)]),
         "fftcg_poll_sequence": (I, [P, ctypes.c_uint64, P, P, P, ctypes.POINTER(Info)]),
+        "fftcg_server_completed": (I, [P, ctypes.POINTER(ctypes.c_uint64), I, ctypes.POINTER(I)]),
         "fftcg_server_get_stats": (I, [P, ctypes.POINTER(ServerStats)]),
         "fftcg_server_destroy": (I, [P]),
         "fftcg_strerror": (ctypes.c_char_p, [I]),
@@ -285,6 +286,15 @@ class Server:
         if st in (OK, ENOCONV):
             return Result(st, (x, broken, iters), info.as_dict())
         return Result(st, None, info.as_dict())
+
+    def completed(self, cap=4096):
+        """Tickets finished since the last call (each reported once)."""
+        out = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int()
+        st = load().fftcg_server_completed(self.h, out, int(cap), ctypes.byref(n))
+        if st != OK:
+            raise FftcgError(st, "fftcg_server_completed")
+        return list(out[:n.value])
 
     def stats(self):
         s = ServerStats()

@@ -46,6 +46,7 @@ using namespace fftcg;
 namespace {
 
 constexpr int kMaxSteps = 1024;  // capacity of a slot's broken-index buffer
+constexpr size_t kMaxCompleted = size_t(1) << 20;  // unreported tickets kept
 
 struct Request {
     uint64_t ticket = 0;
@@ -111,6 +112,11 @@ struct fftcg_server_s {
     std::atomic<int> in_flight{0};
     int queued = 0;
     fftcg_server_stats stats{};
+    std::deque<uint64_t> completed;  // finished, not yet reported tickets
+    // pinned host buffers kept for reuse, by size (pinning is slow)
+    std::mutex pin_mu;
+    std::multimap<size_t, void*> pin_free;
+    size_t pin_cached = 0;
 };
 
 namespace {
@@ -279,6 +285,8 @@ void finish_request(fftcg_server_s* srv, Request* q, int status, const SolveStat
     q->info.lambda_lb = st.lam_lb;
     q->info.device_ms = 0.0;
     q->done = true;
+    srv->completed.push_back(q->ticket);
+    if (srv->completed.size() > kMaxCompleted) srv->completed.pop_front();
     if (status == FFTCG_OK || status == FFTCG_ENOCONV)
         srv->stats.completed += 1;
     else if (status == FFTCG_ECANCELED)
@@ -424,10 +432,42 @@ bool all_finite(const double* a, size_t n) {
     return true;
 }
 
-void free_request_buffers(Request* q) {
-    if (q->pin_in) (void)hipHostFree(q->pin_in);
-    if (q->pin_x) (void)hipHostFree(q->pin_x);
-    if (q->pin_broken) (void)hipHostFree(q->pin_broken);
+constexpr size_t kPinCacheBytes = size_t(2) << 30;
+
+// Pinned host buffer of exactly `bytes`, reused from the pool when possible.
+void* pin_get(fftcg_server_s* srv, size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(srv->pin_mu);
+        auto it = srv->pin_free.find(bytes);
+        if (it != srv->pin_free.end()) {
+            void* p = it->second;
+            srv->pin_free.erase(it);
+            srv->pin_cached -= bytes;
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void pin_put(fftcg_server_s* srv, void* p, size_t bytes) {
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->pin_mu);
+        if (srv->pin_cached + bytes <= kPinCacheBytes) {
+            srv->pin_free.emplace(bytes, p);
+            srv->pin_cached += bytes;
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+}
+
+void free_request_buffers(fftcg_server_s* srv, Request* q) {
+    pin_put(srv, q->pin_in, q->n * 8 * 4);
+    pin_put(srv, q->pin_x, q->n * 8);
+    pin_put(srv, q->pin_broken, sizeof(int) * (size_t)q->steps);
     q->pin_in = q->pin_x = nullptr;
     q->pin_broken = nullptr;
 }
@@ -480,12 +520,11 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     q->steps = steps;
     q->n = n;
     q->has_x0 = x0 != nullptr;
-    bool ok = hipHostMalloc((void**)&q->pin_in, n * 8 * 4, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc((void**)&q->pin_x, n * 8, hipHostMallocDefault) == hipSuccess &&
-              (steps == 0 ||
-               hipHostMalloc((void**)&q->pin_broken, sizeof(int) * steps, hipHostMallocDefault) == hipSuccess);
-    if (!ok) {
-        free_request_buffers(q.get());
+    q->pin_in = (double*)pin_get(srv, n * 8 * 4);
+    q->pin_x = (double*)pin_get(srv, n * 8);
+    if (steps > 0) q->pin_broken = (int*)pin_get(srv, sizeof(int) * steps);
+    if (!q->pin_in || !q->pin_x || (steps > 0 && !q->pin_broken)) {
+        free_request_buffers(srv, q.get());
         return FFTCG_ENOMEM;
     }
     memcpy(q->pin_in, d, n * 8);
@@ -494,7 +533,7 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     if (t) memcpy(q->pin_in + 3 * n, t, n * 8);
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->queued >= srv->opts.queue_cap) {
-        free_request_buffers(q.get());
+        free_request_buffers(srv, q.get());
         return FFTCG_EAGAIN;
     }
     Class* c = nullptr;
@@ -502,7 +541,7 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     if (it == srv->classes.end()) {
         const int rc = make_class(srv, plan, precision, &c);
         if (rc != FFTCG_OK) {
-            free_request_buffers(q.get());
+            free_request_buffers(srv, q.get());
             return rc;
         }
     } else {
@@ -552,7 +591,7 @@ static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* brok
             for (int i = 0; i < q->steps; ++i) step_iters[i] = i < (int)q->step_iters.size() ? q->step_iters[i] : -1;
     }
     if (info) *info = q->info;
-    free_request_buffers(q.get());
+    free_request_buffers(srv, q.get());
     return st;
 }
 
@@ -563,6 +602,18 @@ extern "C" int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_
 extern "C" int fftcg_poll_sequence(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
                                    fftcg_info* info) {
     return poll_common(srv, ticket, x, broken, step_iters, info, true);
+}
+
+extern "C" int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap, int* n) {
+    if (!srv || !n || cap < 0 || (cap > 0 && !out)) return FFTCG_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    int k = 0;
+    while (k < cap && !srv->completed.empty()) {
+        out[k++] = srv->completed.front();
+        srv->completed.pop_front();
+    }
+    *n = k;
+    return FFTCG_OK;
 }
 
 extern "C" int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out) {
@@ -584,8 +635,9 @@ extern "C" int fftcg_server_destroy(fftcg_server_t srv) {
     for (auto& kv : srv->requests) {
         Request* q = kv.second.get();
         if (!q->done) q->plan->refs.fetch_sub(1);
-        free_request_buffers(q);
+        free_request_buffers(srv, q);
     }
+    for (auto& kv : srv->pin_free) (void)hipHostFree(kv.second);
     delete srv;
     return FFTCG_OK;
 }

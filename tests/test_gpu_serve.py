@@ -74,6 +74,11 @@ def test_alone_equals_mix(plans):
             assert np.array_equal(res[tk].x, xa)
     stats = srv.stats()
     assert stats["completed"] == 3 * len(reqs) and stats["failed"] == 0
+    # every ticket reported as completed exactly once
+    seen = srv.completed(cap=7) + srv.completed(cap=100)
+    assert len(seen) == 3 * len(reqs) and len(set(seen)) == len(seen)
+    assert set(tks) <= set(seen)
+    assert srv.completed() == []
     srv.close()
     # accuracy against the oracle
     for r, xa in zip(reqs[:4], alone[:4]):
