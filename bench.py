@@ -89,6 +89,19 @@ def cpu_baseline(inst, gpu_iters, max_seconds=20.0):
     }
 
 
+def oracle_certify(insts, xs):
+    """Largest certified error bound of the GPU solutions xs, from the
+    oracle's FP64 residual b - A x (numpy-FFT product) and its lambda_lb."""
+    import numpy as np
+    from oracle import apply_fft, lambda_lb, error_bound
+    out = []
+    for inst, x in zip(insts, xs):
+        r = inst["b"] - apply_fft(inst["ghat"], inst["d"], x, inst["padded"])
+        out.append(error_bound(float(np.linalg.norm(r)), float(np.linalg.norm(x)),
+                               lambda_lb(inst["ghat"], inst["d"])))
+    return max(out)
+
+
 def _pct(v, q):
     """Nearest-rank percentile."""
     v = sorted(v)
@@ -112,7 +125,7 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
     plans = {M: binding.Plan(M // 2, 1, spectrum(M, 1e-3)) for M in (128, 256, 512, 1024)}
     reqs = [c4_request(k, int(M)) for k, M in enumerate(sizes)]
 
-    def run_served():
+    def run_served(budget=budget, n=len(reqs)):
         srv = binding.Server(memory_budget=budget, chunk_iters=chunk)
         # warm-up: one request per size (allocates slots, loads kernels)
         tks = []
@@ -128,9 +141,9 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
         lat, iters, bad = [], [], 0
         t0 = time.perf_counter()
         k = 0
-        while k < len(reqs) or outstanding:
+        while k < n or outstanding:
             now = time.perf_counter() - t0
-            while k < len(reqs) and arrivals[k] <= now:
+            while k < n and arrivals[k] <= now:
                 r = reqs[k]
                 st, tk = srv.submit(plans[r["M"]], r["d"], r["b"], tol=1e-8)
                 if st == binding.OK:
@@ -148,7 +161,7 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
                 if res.status != binding.OK:
                     bad += 1
             if not done:
-                nxt = arrivals[k] - (time.perf_counter() - t0) if k < len(reqs) else 2e-4
+                nxt = arrivals[k] - (time.perf_counter() - t0) if k < n else 2e-4
                 time.sleep(max(0.0, min(2e-4, nxt)))
         makespan = time.perf_counter() - t0
         stats = srv.stats()
@@ -156,6 +169,27 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
         return dict(p50_ms=_pct(lat, 50) * 1e3, p99_ms=_pct(lat, 99) * 1e3, solves_per_s=len(lat) / makespan,
                     makespan_s=makespan, failed=bad, mean_iters=float(np.mean(iters)),
                     peak_bytes=stats["bytes_in_use"])
+
+    def run_closed_loop():
+        """Every request released at t = 0: the server's peak throughput."""
+        srv = binding.Server(memory_budget=budget, chunk_iters=chunk)
+        t0 = time.perf_counter()
+        left = {}
+        for r in reqs:
+            st, tk = srv.submit(plans[r["M"]], r["d"], r["b"], tol=1e-8)
+            if st == binding.OK:
+                left[tk] = r["L"]
+        bad = len(reqs) - len(left)
+        while left:
+            done = srv.completed()
+            for tk in done:
+                if srv.poll(tk, left.pop(tk)).status != binding.OK:
+                    bad += 1
+            if not done:
+                time.sleep(2e-4)
+        makespan = time.perf_counter() - t0
+        srv.close()
+        return dict(solves_per_s=len(reqs) / makespan, makespan_s=makespan, failed=bad)
 
     def run_fp64_sequential():
         dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda")  # noqa: E731
@@ -183,12 +217,118 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
                     makespan_s=makespan, failed=bad)
 
     served = run_served()
+    closed = run_closed_loop()
+    tight = run_served(budget=64 << 20, n=min(len(reqs), 500))
     base = run_fp64_sequential()
     return dict(requests=n_requests, arrival_rate_per_s=round(n_requests / float(arrivals[-1]), 1),
                 budget_bytes=budget,
                 served_mixed={k: (round(v, 3) if isinstance(v, float) else v) for k, v in served.items()},
+                closed_loop_mixed={k: (round(v, 3) if isinstance(v, float) else v) for k, v in closed.items()},
+                tight_budget_64MiB_first500={k: (round(v, 3) if isinstance(v, float) else v)
+                                             for k, v in tight.items()},
                 fp64_one_at_a_time={k: (round(v, 3) if isinstance(v, float) else v) for k, v in base.items()},
                 speedup_solves_per_s=round(served["solves_per_s"] / base["solves_per_s"], 2))
+
+
+def solve_set_bench(insts, precision, tol):
+    """fftcg_solve one instance at a time (device-resident inputs), then the
+    same set submitted to the server at once (batched slots)."""
+    import numpy as np
+    import torch
+    from paper_1305_3625_amd import binding
+    L, padded = insts[0]["L"], insts[0]["padded"]
+    M = insts[0]["M"]
+    plan = binding.Plan(L, padded, insts[0]["ghat"])
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda")  # noqa: E731
+    D = [dev(i["d"]) for i in insts]
+    B = [dev(i["b"]) for i in insts]
+    X = [torch.zeros((L, L), dtype=torch.float64, device="cuda") for _ in insts]
+    plan.solve(D[0], B[0], X[0], tol=tol, precision=precision)
+    torch.cuda.synchronize()
+    infos, per = [], []
+    t0 = time.perf_counter()
+    for j in range(len(insts)):
+        t1 = time.perf_counter()
+        infos.append(plan.solve(D[j], B[j], X[j], tol=tol, precision=precision))
+        per.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    bad = sum(inf["status"] != binding.OK for inf in infos)
+    iters = [inf["iterations"] for inf in infos]
+    checks = [inf["checks"] for inf in infos]
+    out = dict(instances=len(insts), L=L, M=M, padded=padded, tol=tol,
+               precision="fp64" if precision == binding.FP64 else "mixed",
+               solves_per_s=round(len(insts) / elapsed, 2),
+               ms_per_solve_median=round(float(np.median(per)) * 1e3, 4),
+               ms_per_solve_min=round(float(np.min(per)) * 1e3, 4),
+               iterations_mean=round(float(np.mean(iters)), 2), checks_mean=round(float(np.mean(checks)), 2),
+               matvecs_per_s=round((sum(iters) + sum(checks)) / elapsed, 1),
+               fft_gflops_nominal=round((sum(iters) + sum(checks)) / elapsed * fft_flops_nominal(M) / 1e9, 2),
+               error_bound_max=max(inf["error_bound"] for inf in infos), failed=bad)
+    # batched: every instance in flight at once through the server
+    srv = binding.Server(memory_budget=4 << 30, max_slots=len(insts))
+    tks = []
+    t0 = time.perf_counter()
+    for inst in insts:
+        st, tk = srv.submit(plan, inst["d"], inst["b"], tol=tol, precision=precision)
+        if st != binding.OK:
+            raise SystemExit(f"submit failed: {binding.STATUS_NAMES.get(st, st)}")
+        tks.append(tk)
+    left = set(tks)
+    while left:
+        done = srv.completed()
+        for tk in done:
+            left.discard(tk)
+            if srv.poll(tk, L).status != binding.OK:
+                bad += 1
+        if not done:
+            time.sleep(2e-4)
+    out["batched_solves_per_s"] = round(len(insts) / (time.perf_counter() - t0), 2)
+    out["failed"] = bad
+    srv.close()
+    plan.close()
+    return out
+
+
+def loadstep_bench(n_seq=64, steps=1000):
+    """Load-stepped sequences (warm-started solves, device argmax break rule),
+    all submitted to the server at once."""
+    import numpy as np
+    from paper_1305_3625_amd import binding
+    from workloads import c5_sequence, spectrum
+    seqs = [c5_sequence(s) for s in range(n_seq)]
+    L = seqs[0]["L"]
+    plan = binding.Plan(L, 1, spectrum(2 * L, seqs[0]["eps"]))
+    srv = binding.Server(memory_budget=4 << 30, max_slots=n_seq)
+    st, tk = srv.submit_sequence(plan, seqs[0]["d"], seqs[0]["b"], seqs[0]["t"], 2, tol=1e-8)
+    while srv.poll_sequence(tk, L, 2).status == binding.PENDING:
+        time.sleep(1e-3)
+    srv.completed()
+    t0 = time.perf_counter()
+    tks = {}
+    for q in seqs:
+        st, tk = srv.submit_sequence(plan, q["d"], q["b"], q["t"], steps, tol=1e-8)
+        if st != binding.OK:
+            raise SystemExit(f"submit_sequence failed: {binding.STATUS_NAMES.get(st, st)}")
+        tks[tk] = q
+    iters, bad = [], 0
+    while tks:
+        done = srv.completed()
+        for tk in done:
+            tks.pop(tk)
+            res = srv.poll_sequence(tk, L, steps)
+            if res.status != binding.OK:
+                bad += 1
+            else:
+                iters.extend(res.x[2].tolist())
+        if not done:
+            time.sleep(1e-3)
+    elapsed = time.perf_counter() - t0
+    srv.close()
+    plan.close()
+    return dict(sequences=n_seq, steps=steps, L=L, solves=n_seq * steps, makespan_s=round(elapsed, 3),
+                solves_per_s=round(n_seq * steps / elapsed, 1),
+                iterations_per_step_mean=round(float(np.mean(iters)), 2) if iters else None, failed=bad)
 
 
 def main(argv=None):
@@ -203,6 +343,11 @@ def main(argv=None):
                     help="also run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the open-loop serving workload (0: skip; 20000: the full schedule)")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the other workloads (periodic L=64 and padded L=512 FP64 sets, load-stepped "
+                         "sequences)")
+    ap.add_argument("--seq", type=int, default=64, help="load-stepped sequences")
+    ap.add_argument("--seq-steps", type=int, default=1000, help="load steps per sequence")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (a single solve does not "
@@ -277,24 +422,29 @@ def main(argv=None):
     copy_gbps = 2 * src.numel() * 8 * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del src, dst
 
-    # oracle certification of each instance's GPU solution (FP64 residual)
-    oracle_bounds = None
-    if not a.no_oracle_check:
-        from oracle import apply_fft, lambda_lb, error_bound
-        oracle_bounds = []
-        for j, inst in enumerate(insts[: min(len(insts), a.steps)]):
-            x = X[j].cpu().numpy()
-            r = inst["b"] - apply_fft(inst["ghat"], inst["d"], x, 1)
-            oracle_bounds.append(error_bound(float(np.linalg.norm(r)), float(np.linalg.norm(x)),
-                                             lambda_lb(inst["ghat"], inst["d"])))
-
+    # CPU leg: the oracle timed on a bounded sample, and its FP64 residual of
+    # each instance's GPU solution (certified error bound)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(insts[0], infos[0]["iterations"])
+        if not a.no_oracle_check:
+            xs = [X[j].cpu().numpy() for j in range(min(len(insts), a.steps))]
+            cpu["oracle_error_bound_max"] = oracle_certify(insts, xs)
 
     served = None
     if a.serve_requests > 0:
         served = serve_bench(a.serve_requests)
+
+    other = None
+    if not a.no_other:
+        from workloads import c1_instance, c2_instance
+        other = {
+            "periodic_L64_fp64_100_instances": solve_set_bench([c1_instance(s) for s in range(100)],
+                                                               binding.FP64, 1e-10),
+            "padded_L512_fp64_10_instances": solve_set_bench([c2_instance(s) for s in range(10)],
+                                                             binding.FP64, 1e-10),
+            "loadstep_L512_mixed": loadstep_bench(a.seq, a.seq_steps) if a.seq > 0 else None,
+        }
 
     out = {
         "metric": METRIC,
@@ -338,9 +488,9 @@ def main(argv=None):
         "product_fp32_GBps": round(bm["apply"] / (sum(passes32) * 1e-3) / 1e9, 1),
         "product_fp64_ms": [round(v, 5) for v in passes64],
         "device_error_bound_max": max(inf["error_bound"] for inf in infos),
-        "oracle_error_bound_max": None if oracle_bounds is None else max(oracle_bounds),
         "plan_ms": round(plan_ms, 2),
         "served": served,
+        "other_workloads": other,
     }
     print(json.dumps(out), flush=True)
 
