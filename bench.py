@@ -171,25 +171,30 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
                     peak_bytes=stats["bytes_in_use"])
 
     def run_closed_loop():
-        """Every request released at t = 0: the server's peak throughput."""
+        """Every request released at t = 0: the server's peak throughput, on a
+        fresh server (cold: its slots and pinned staging are allocated on the
+        way) and again on the same server (warm)."""
         srv = binding.Server(memory_budget=budget, chunk_iters=chunk)
-        t0 = time.perf_counter()
-        left = {}
-        for r in reqs:
-            st, tk = srv.submit(plans[r["M"]], r["d"], r["b"], tol=1e-8)
-            if st == binding.OK:
-                left[tk] = r["L"]
-        bad = len(reqs) - len(left)
-        while left:
-            done = srv.completed()
-            for tk in done:
-                if srv.poll(tk, left.pop(tk)).status != binding.OK:
-                    bad += 1
-            if not done:
-                time.sleep(2e-4)
-        makespan = time.perf_counter() - t0
+        out = {}
+        for label in ("cold", "warm"):
+            t0 = time.perf_counter()
+            left = {}
+            for r in reqs:
+                st, tk = srv.submit(plans[r["M"]], r["d"], r["b"], tol=1e-8)
+                if st == binding.OK:
+                    left[tk] = r["L"]
+            bad = len(reqs) - len(left)
+            while left:
+                done = srv.completed()
+                for tk in done:
+                    if srv.poll(tk, left.pop(tk)).status != binding.OK:
+                        bad += 1
+                if not done:
+                    time.sleep(2e-4)
+            makespan = time.perf_counter() - t0
+            out[label] = dict(solves_per_s=len(reqs) / makespan, makespan_s=makespan, failed=bad)
         srv.close()
-        return dict(solves_per_s=len(reqs) / makespan, makespan_s=makespan, failed=bad)
+        return out
 
     def run_fp64_sequential():
         dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda")  # noqa: E731
@@ -223,7 +228,8 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
     return dict(requests=n_requests, arrival_rate_per_s=round(n_requests / float(arrivals[-1]), 1),
                 budget_bytes=budget,
                 served_mixed={k: (round(v, 3) if isinstance(v, float) else v) for k, v in served.items()},
-                closed_loop_mixed={k: (round(v, 3) if isinstance(v, float) else v) for k, v in closed.items()},
+                closed_loop_mixed={lab: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+                                   for lab, d in closed.items()},
                 tight_budget_64MiB_first500={k: (round(v, 3) if isinstance(v, float) else v)
                                              for k, v in tight.items()},
                 fp64_one_at_a_time={k: (round(v, 3) if isinstance(v, float) else v) for k, v in base.items()},
@@ -265,25 +271,27 @@ def solve_set_bench(insts, precision, tol):
                matvecs_per_s=round((sum(iters) + sum(checks)) / elapsed, 1),
                fft_gflops_nominal=round((sum(iters) + sum(checks)) / elapsed * fft_flops_nominal(M) / 1e9, 2),
                error_bound_max=max(inf["error_bound"] for inf in infos), failed=bad)
-    # batched: every instance in flight at once through the server
+    # batched: every instance in flight at once through the server; the
+    # first round also creates the slots (cold), the second reuses them (warm)
     srv = binding.Server(memory_budget=4 << 30, max_slots=len(insts))
-    tks = []
-    t0 = time.perf_counter()
-    for inst in insts:
-        st, tk = srv.submit(plan, inst["d"], inst["b"], tol=tol, precision=precision)
-        if st != binding.OK:
-            raise SystemExit(f"submit failed: {binding.STATUS_NAMES.get(st, st)}")
-        tks.append(tk)
-    left = set(tks)
-    while left:
-        done = srv.completed()
-        for tk in done:
-            left.discard(tk)
-            if srv.poll(tk, L).status != binding.OK:
-                bad += 1
-        if not done:
-            time.sleep(2e-4)
-    out["batched_solves_per_s"] = round(len(insts) / (time.perf_counter() - t0), 2)
+    for label in ("cold", "warm"):
+        tks = []
+        t0 = time.perf_counter()
+        for inst in insts:
+            st, tk = srv.submit(plan, inst["d"], inst["b"], tol=tol, precision=precision)
+            if st != binding.OK:
+                raise SystemExit(f"submit failed: {binding.STATUS_NAMES.get(st, st)}")
+            tks.append(tk)
+        left = set(tks)
+        while left:
+            done = srv.completed()
+            for tk in done:
+                left.discard(tk)
+                if srv.poll(tk, L).status != binding.OK:
+                    bad += 1
+            if not done:
+                time.sleep(2e-4)
+        out[f"batched_{label}_solves_per_s"] = round(len(insts) / (time.perf_counter() - t0), 2)
     out["failed"] = bad
     srv.close()
     plan.close()

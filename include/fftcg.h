@@ -64,11 +64,13 @@ extern "C" {
 #define FFTCG_MIXED 1
 
 /* ---- engines (fftcg_plan_set_engine) -----------------------------------
- * AUTO     : fused single-workgroup engine for M <= 64, multi-pass above.
+ * AUTO     : the fused engine for L <= 64 (single solves and server
+ *            classes alike), the multi-pass engine above.
  * MULTIPASS: three HBM passes per product (row R2C, column FFT*ghat*IFFT,
  *            row C2R + epilogue); every grid.
- * FUSED    : one workgroup per solve, whole CG loop in one kernel with the
- *            product in LDS; M <= 64.                                       */
+ * FUSED    : one workgroup per solve, whole CG loop in one kernel, the
+ *            product's half spectrum in the slot's buffer (L1/L2-resident)
+ *            and its transforms in registers and LDS; M <= 256.            */
 #define FFTCG_ENGINE_AUTO      0
 #define FFTCG_ENGINE_MULTIPASS 1
 #define FFTCG_ENGINE_FUSED     2
@@ -206,7 +208,9 @@ int fftcg_submit_sequence(fftcg_server_t srv, fftcg_plan_t plan, int precision,
 
 /* fftcg_poll -- FFTCG_PENDING, or the request's final status with x (HOST
  * pointer, L*L doubles) and info copied out; the ticket is then retired and
- * later polls return FFTCG_ENOTFOUND.  x or info may be NULL.              */
+ * later polls return FFTCG_ENOTFOUND.  x or info may be NULL.  FFTCG_ENOMEM
+ * if no pinned host buffer for the result could be allocated when the solve
+ * finished (x is then not written).                                        */
 int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info);
 
 /* fftcg_poll_sequence -- like fftcg_poll for a sequence ticket; also copies

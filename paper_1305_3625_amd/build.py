@@ -1,8 +1,8 @@
 """Builds libfftcg.so (HIP, gfx950 only) in-tree.
 
 Every source under ``csrc/`` is compiled with hipcc for ``--offload-arch=gfx950``;
-the multi-pass engine source is compiled once per grid size and boundary
-condition.  Objects go to ``_build/`` at the repository root and the library
+the multi-pass and fused engine sources are compiled once per grid size and
+boundary condition.  Objects go to ``_build/`` at the repository root and the library
 to ``paper_1305_3625_amd/libfftcg.so``.
 
     python -m paper_1305_3625_amd.build [--jobs N]
@@ -38,6 +38,8 @@ CXXFLAGS = [
 ENGINE_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)] + \
                [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)]
 
+FUSED_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256)] + [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256)]
+
 SOURCES = ["fftcg_host.cpp", "common.hip", "fused.hip", "server.cpp"]
 
 
@@ -59,6 +61,9 @@ def _jobs(build_dir, extra):
     for m, pad in ENGINE_SIZES:
         yield [HIPCC, *CXXFLAGS, *extra, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", "-c",
                os.path.join(CSRC, "engine_inst.hip"), "-o", obj(f"engine_{m}_{pad}")]
+    for m, pad in FUSED_SIZES:
+        yield [HIPCC, *CXXFLAGS, *extra, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", "-c",
+               os.path.join(CSRC, "fused_inst.hip"), "-o", obj(f"fused_{m}_{pad}")]
 
 
 def build(jobs: int | None = None, verbose: bool = False, extra_flags=(), lib_path: str = LIB,

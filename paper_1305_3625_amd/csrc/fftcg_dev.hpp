@@ -24,6 +24,39 @@ struct cx {
     T x, y;
 };
 
+// Pointers into device memory (HBM) reached through the slot table are
+// generic pointers to the compiler; in the global address space its loads
+// and stores are global_* instructions, which count only in vmcnt and so do
+// not hold up LDS traffic the way flat_* instructions do.
+template <typename T>
+struct GlobalT {
+    typedef __attribute__((address_space(1))) T type;
+};
+template <typename T>
+__device__ __forceinline__ typename GlobalT<T>::type* gbl(T* p) {
+    return (typename GlobalT<T>::type*)p;
+}
+// Plain vector types (no constructors), loadable through such pointers.
+template <typename T, int K>
+struct VecT {
+    typedef T type __attribute__((ext_vector_type(K)));
+};
+template <typename T>
+__device__ __forceinline__ cx<T> gld(const cx<T>* p) {
+    const auto v = *gbl(reinterpret_cast<const typename VecT<T, 2>::type*>(p));
+    cx<T> c;
+    c.x = v.x;
+    c.y = v.y;
+    return c;
+}
+template <typename T>
+__device__ __forceinline__ void gst(cx<T>* p, cx<T> c) {
+    typename VecT<T, 2>::type v;
+    v.x = c.x;
+    v.y = c.y;
+    *gbl(reinterpret_cast<typename VecT<T, 2>::type*>(p)) = v;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> mkc(T a, T b) {
     cx<T> r;
@@ -202,17 +235,17 @@ __device__ __forceinline__ void twiddle_run(cx<T>* v, const cx<T>* __restrict__ 
     // variant: one table read per power
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-        cx<T> w = tw[r * m];
+        cx<T> w = gld(tw + r * m);
         if (DIR > 0) w.y = -w.y;
         v[r] = cmul(v[r], w);
     }
     return;
 #endif
     cx<T> p[16];
-    p[1] = tw[m];
-    if constexpr (R > 2) p[2] = tw[2 * m];
-    if constexpr (R > 4) p[4] = tw[4 * m];
-    if constexpr (R > 8) p[8] = tw[8 * m];
+    p[1] = gld(tw + m);
+    if constexpr (R > 2) p[2] = gld(tw + 2 * m);
+    if constexpr (R > 4) p[4] = gld(tw + 4 * m);
+    if constexpr (R > 8) p[8] = gld(tw + 8 * m);
     if constexpr (R > 3) p[3] = cmul(p[1], p[2]);
     if constexpr (R > 5) {
         p[5] = cmul(p[1], p[4]);
@@ -327,7 +360,8 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 template <int NT>
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+    const auto* g = gbl(p);
+    for (int i = threadIdx.x; i < n; i += NT) s += g[i];
     return block_sum<NT>(s, sh);
 }
 

@@ -307,10 +307,18 @@ extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) {
     return FFTCG_OK;
 }
 
+// AUTO picks the fused engine for grids of at most 64 x 64 unknowns: there
+// one workgroup per solve beats four kernel launches per iteration (measured
+// on MI355X: 19-31 us against 30-45 us per product up to L = 64); from
+// L = 128 on, the fused engine's serial rounds cost more than the launches
+// and the multi-pass engine takes over, for single solves and server classes.
 int fftcg::plan_engine(const fftcg_plan_s* p) {
-    if (p->engine == FFTCG_ENGINE_AUTO) return p->fused_ok ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
+    if (p->engine == FFTCG_ENGINE_AUTO)
+        return p->fused_ok && p->L <= 64 ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
     return p->engine;
 }
+
+int fftcg::server_engine(const fftcg_plan_s* p) { return plan_engine(p); }
 
 extern "C" int fftcg_plan_set_engine(fftcg_plan_t plan, int engine) {
     if (!plan) return FFTCG_EINVAL;

@@ -50,6 +50,10 @@ int solve_validate(fftcg_plan_t plan, int precision, const void* d, const void* 
 
 }  // namespace fftcg
 
+namespace fftcg {
+struct FusedOps;
+}
+
 struct fftcg_plan_s {
     int L = 0, M = 0, pad = 0, device = 0;
     int engine = FFTCG_ENGINE_AUTO;
@@ -67,8 +71,9 @@ struct fftcg_plan_s {
     size_t device_bytes = 0;
     void* apply_W = nullptr;
     hipEvent_t apply_ev = nullptr;
-    // fused (single-workgroup) engine tables
+    // fused (single-workgroup) engine: compiled size and constant tables
     int fused_ok = 0;
+    const fftcg::FusedOps* fops = nullptr;
     void* f_tab64 = nullptr;  // per-plan constant tables of the fused engine
     void* f_tab32 = nullptr;
     size_t fused_bytes = 0;
@@ -81,6 +86,7 @@ struct fftcg_plan_s {
 
 namespace fftcg {
 int plan_engine(const fftcg_plan_s* p);
+int server_engine(const fftcg_plan_s* p);
 Workspace* plan_acquire(fftcg_plan_s* p);
 void plan_release(fftcg_plan_s* p, Workspace* w);
 }  // namespace fftcg

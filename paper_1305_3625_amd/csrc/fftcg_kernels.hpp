@@ -222,22 +222,17 @@ struct PairT<float, 2> { using type = float2; };
 template <>
 struct PairT<double, 2> { using type = double2; };
 
+// a pair of consecutive elements (even index) of a device array
 template <typename T>
 __device__ __forceinline__ cx<T> ld2(const T* p) {
-    using V = typename PairT<T, 2>::type;
-    V v = *reinterpret_cast<const V*>(p);
-    return mkc(v.x, v.y);
+    return gld(reinterpret_cast<const cx<T>*>(p));
 }
 template <typename T>
 __device__ __forceinline__ void st2(T* p, cx<T> c) {
-    using V = typename PairT<T, 2>::type;
-    V v;
-    v.x = c.x;
-    v.y = c.y;
-    *reinterpret_cast<V*>(p) = v;
+    gst(reinterpret_cast<cx<T>*>(p), c);
 }
 __device__ __forceinline__ cx<double> ld2f(const float* p) {
-    float2 v = *reinterpret_cast<const float2*>(p);
+    const cx<float> v = gld(reinterpret_cast<const cx<float>*>(p));
     return mkc((double)v.x, (double)v.y);
 }
 
@@ -475,7 +470,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
             const cx<T> wd = cmul(tab.tw[k], d1);
             out = mkc(T(0.5) * (s1.x + wd.y), T(0.5) * (s1.y - wd.x));
         }
-        Wb[((size_t)kt * L + rb * RPW + il) * TT + kk] = out;
+        gst(Wb + ((size_t)kt * L + rb * RPW + il) * TT + kk, out);
     }
 }
 
@@ -501,11 +496,22 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
         for (int r = 0; r < R1; ++r) {
             if (PAD && r >= R1 / 2) continue;
             const int n = (j + u * P) + r * (M / R1);
-            v[u * R1 + r] = Wt[(size_t)n * TT + kk];
+            v[u * R1 + r] = gld(Wt + (size_t)n * TT + kk);
         }
-    fft_run<T, M, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
     constexpr int RL = fft_radix(M, false, NSTG - 1);
     const T* g = tab.ghq + (size_t)kt * MH * TT;
+    // the spectrum values this thread multiplies by, requested together with
+    // the column data so their latency is not exposed after the transform
+    T gpre[E];
+#pragma unroll
+    for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int m = (j + u * P) + r * (M / RL);
+            const int mp = m <= M - m ? m : M - m;
+            gpre[u * RL + r] = g[mp * TT + kk];
+        }
+    fft_run<T, M, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
     if (kt == 0) {
         // packed column 0 carries k = 0 (real part) and k = M/2 (imaginary
         // part): result(m) = s(m) W(m) + t(m) conj(W(M - m)),
@@ -522,11 +528,11 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
                 const cx<T> a = v[u * RL + r];
                 if (kk == 0) {
                     const cx<T> bm = conjc(lay.ld((M - m) & (M - 1)));
-                    const T g0 = g[mp * TT], gN = tab.ghN[mp];
+                    const T g0 = gpre[u * RL + r], gN = tab.ghN[mp];
                     const T s = T(0.5) * (g0 + gN), t = T(0.5) * (g0 - gN);
                     v[u * RL + r] = mkc(s * a.x + t * bm.x, s * a.y + t * bm.y);
                 } else {
-                    v[u * RL + r] = scalec(a, g[mp * TT + kk]);
+                    v[u * RL + r] = scalec(a, gpre[u * RL + r]);
                 }
             }
         __syncthreads();
@@ -537,7 +543,7 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
             for (int r = 0; r < RL; ++r) {
                 const int m = (j + u * P) + r * (M / RL);
                 const int mp = m <= M - m ? m : M - m;
-                v[u * RL + r] = scalec(v[u * RL + r], g[mp * TT + kk]);
+                v[u * RL + r] = scalec(v[u * RL + r], gpre[u * RL + r]);
             }
     }
     fft_run<T, M, M, +1, true, false>(v, lay, j, tab.tw);
@@ -548,7 +554,7 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
         for (int r = 0; r < RZ; ++r) {
             if (PAD && r >= RZ / 2) continue;
             const int n = (j + u * P) + r * (M / RZ);
-            Wt[(size_t)n * TT + kk] = v[u * RZ + r];
+            gst(Wt + (size_t)n * TT + kk, v[u * RZ + r]);
         }
 }
 
@@ -573,7 +579,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
         const int il = (qi / TT) % RPW;
         const int kt = qi / (TT * RPW);
         LdsLay<T, 1, 4, 1> l2{lds + il * WORDS, 0};
-        l2.st(kt * TT + kk, Wb[((size_t)kt * L + row0 + il) * TT + kk]);
+        l2.st(kt * TT + kk, gld(Wb + ((size_t)kt * L + row0 + il) * TT + kk));
     }
     __syncthreads();
     LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
@@ -646,13 +652,13 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
     if (!GateIter::ok(sd)) return;
     SolveState* st = sd.st;
     constexpr int VW = sizeof(W) == 4 ? 4 : 2;
-    using V = typename std::conditional<sizeof(W) == 4, float4, double2>::type;
+    using V = typename VecT<W, VW>::type;
     const int nv = n / VW;
     const int per = (nv + gridDim.x - 1) / gridDim.x;
     const int lo = blockIdx.x * per;
     const int hi = lo + per < nv ? lo + per : nv;
-    V* r = reinterpret_cast<V*>(sd.r);
-    const V* q = reinterpret_cast<const V*>(sd.q);
+    auto* r = gbl(reinterpret_cast<V*>(sd.r));
+    const auto* q = gbl(reinterpret_cast<const V*>(sd.q));
     // the first PF vectors of r and q are requested before the p.q reduction
     // so its latency overlaps the HBM reads
     constexpr int PF = 4;

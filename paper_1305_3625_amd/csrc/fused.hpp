@@ -1,6 +1,6 @@
-// Fused single-workgroup engine for small grids (M <= 128): one workgroup
-// holds a whole solve; the operator product and the CG update run in LDS
-// with no kernel boundary between iterations.
+// Fused single-workgroup engine for small grids (M <= 256): one workgroup
+// holds a whole solve; the operator product and the CG update run with no
+// kernel boundary between iterations.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -10,6 +10,27 @@
 struct fftcg_plan_s;
 
 namespace fftcg {
+
+// Per-plan constant tables (device pointers).
+struct FusedTabs {
+    const void* tw64;  // cx<double>[M]: exp(-2 pi i m / M)
+    const void* tw32;  // cx<float>[M]
+    const void* gq64;  // double[(M/2+1)^2]: ghat(m, k) / M^2, m, k in [0, M/2], row-major
+    const void* gq32;  // float[(M/2+1)^2]
+};
+
+// Launchers of one compiled size (precision 0 = FP64, 1 = FP32 inner
+// iterations / operator).
+struct FusedOps {
+    int M, pad;
+    int lds_bytes;  // exchange buffer of a solve workgroup
+    void (*solve)(int prec, const FusedTabs& ft, const SlotDesc* slots, int nslots, int max_iters,
+                  hipStream_t s);
+    void (*apply)(int prec, const FusedTabs& ft, const double* d, const double* x, double* y, void* W,
+                  hipStream_t s);
+};
+
+const FusedOps* find_fused(int M, int pad);
 
 int fused_init(fftcg_plan_s* p, const double* spectrum);
 void fused_free(fftcg_plan_s* p);

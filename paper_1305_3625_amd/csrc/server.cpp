@@ -21,6 +21,7 @@
 // retirement.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -56,10 +57,13 @@ struct Request {
     int maxit = 0;
     int steps = 0;  // 0: one solve; > 0: load-stepped sequence
     size_t n = 0;
-    double* pin_in = nullptr;  // pinned staging: d, b, x0, t
-    double* pin_x = nullptr;   // pinned result
+    double* pin_in = nullptr;  // staging of the inputs: d, b, then x0 and t when given
+    bool in_pinned = true;     // false: pageable (over the pinned cap), staged per slot
+    double* pin_x = nullptr;   // pinned result (taken when the solve retires)
+    bool x_nomem = false;      // no pinned result buffer could be had
     int* pin_broken = nullptr; // pinned sequence result
     bool has_x0 = false;
+    size_t in_bytes = 0;
     int status = FFTCG_PENDING;
     fftcg_info info{};
     std::vector<int> step_iters;
@@ -74,6 +78,7 @@ struct Slot {
     double* t = nullptr;
     int* broken = nullptr;            // device, one entry per step
     SolveState* pin_state = nullptr;  // pinned staging of the state
+    double* stage = nullptr;          // pinned staging of pageable request inputs
     Request* req = nullptr;
     int gen = 0;
     int step = 0;
@@ -116,10 +121,14 @@ struct fftcg_server_s {
     // pinned host buffers kept for reuse, by size (pinning is slow)
     std::mutex pin_mu;
     std::multimap<size_t, void*> pin_free;
-    size_t pin_cached = 0;
+    size_t pin_cached = 0;  // bytes idle in pin_free
+    size_t pin_inputs = 0;  // pinned input staging handed out
+    size_t pin_input_cap = 0;  // a quarter of the device budget, in [1 MiB, 1 GiB]
 };
 
 namespace {
+
+void* pin_get(fftcg_server_s* srv, size_t bytes, bool input, bool* pinned);
 
 size_t slot_footprint(const fftcg_plan_s* p) {
     const size_t n = (size_t)p->L * p->L;
@@ -132,6 +141,8 @@ void free_slot_memory(Slot* s) {
         if (v) (void)hipFree(v);
     if (s->broken) (void)hipFree(s->broken);
     if (s->pin_state) (void)hipHostFree(s->pin_state);
+    if (s->stage) (void)hipHostFree(s->stage);
+    s->stage = nullptr;
     if (s->ev_retire) (void)hipEventDestroy(s->ev_retire);
     s->x = s->b = s->d = s->t = nullptr;
     s->broken = nullptr;
@@ -184,6 +195,7 @@ bool add_slot(fftcg_server_s* srv, Class* c) {
          hipMalloc(&s->d, n * 8) == hipSuccess && hipMalloc(&s->t, n * 8) == hipSuccess &&
          hipMalloc(&s->broken, sizeof(int) * kMaxSteps) == hipSuccess &&
          hipHostMalloc((void**)&s->pin_state, sizeof(SolveState), hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc((void**)&s->stage, n * 8 * 4, hipHostMallocDefault) == hipSuccess &&
          hipEventCreateWithFlags(&s->ev_retire, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         free_slot_memory(s.get());
@@ -260,6 +272,13 @@ void admit(Class* c, Request* q, int idx) {
     s->retiring = false;
     const size_t n = q->n;
     const double* pin = q->pin_in;
+    if (!q->in_pinned) {
+        // pageable inputs go through the slot's pinned staging buffer (free:
+        // its previous request was admitted, and its copies done, before it
+        // retired)
+        memcpy(s->stage, q->pin_in, q->in_bytes);
+        pin = s->stage;
+    }
     hipStream_t st = c->stream;
     (void)hipMemcpyAsync(s->d, pin, n * 8, hipMemcpyHostToDevice, st);
     (void)hipMemcpyAsync(s->b, pin + n, n * 8, hipMemcpyHostToDevice, st);
@@ -267,7 +286,8 @@ void admit(Class* c, Request* q, int idx) {
         (void)hipMemcpyAsync(s->x, pin + 2 * n, n * 8, hipMemcpyHostToDevice, st);
     else
         (void)hipMemsetAsync(s->x, 0, n * 8, st);
-    if (q->steps > 0) (void)hipMemcpyAsync(s->t, pin + 3 * n, n * 8, hipMemcpyHostToDevice, st);
+    if (q->steps > 0)
+        (void)hipMemcpyAsync(s->t, pin + (q->has_x0 ? 3 : 2) * n, n * 8, hipMemcpyHostToDevice, st);
     start_solve(c, idx);
     c->h_table[idx].active = 1;
     upload_entry(c, idx);
@@ -314,7 +334,7 @@ bool progress(fftcg_server_s* srv, Class* c) {
         {
             std::lock_guard<std::mutex> lk(srv->mu);
             if (q->steps > 0) q->step_iters.push_back(st.iters);
-            finish_request(srv, q, st.status, st);
+            finish_request(srv, q, q->x_nomem ? FFTCG_ENOMEM : st.status, st);
         }
         s->req = nullptr;
         s->retiring = false;
@@ -346,7 +366,14 @@ bool progress(fftcg_server_s* srv, Class* c) {
         upload_entry(c, i);
         (void)hipMemcpyAsync(s->pin_state, s->ws->st, sizeof(SolveState), hipMemcpyDeviceToHost, c->stream);
         if (ok) {
-            (void)hipMemcpyAsync(q->pin_x, s->x, q->n * 8, hipMemcpyDeviceToHost, c->stream);
+            // pinned result buffers are taken only now, so a long queue
+            // holds none
+            bool pinned = true;
+            q->pin_x = (double*)pin_get(srv, q->n * 8, false, &pinned);
+            if (q->pin_x)
+                (void)hipMemcpyAsync(q->pin_x, s->x, q->n * 8, hipMemcpyDeviceToHost, c->stream);
+            else
+                q->x_nomem = true;
             if (q->steps > 0)
                 (void)hipMemcpyAsync(q->pin_broken, s->broken, sizeof(int) * q->steps, hipMemcpyDeviceToHost,
                                      c->stream);
@@ -387,7 +414,7 @@ bool progress(fftcg_server_s* srv, Class* c) {
         if (s->req && !s->retiring) active = true;
     if (active && c->inflight < 2) {
         const int nsl = (int)c->slots.size();
-        if (plan_engine(c->plan) == FFTCG_ENGINE_FUSED) {
+        if (server_engine(c->plan) == FFTCG_ENGINE_FUSED) {
             // one workgroup per slot runs the chunk's iterations and checks
             fused_launch(c->plan, c->precision, c->d_table, nsl, srv->opts.chunk_iters, c->stream);
         } else {
@@ -432,10 +459,14 @@ bool all_finite(const double* a, size_t n) {
     return true;
 }
 
-constexpr size_t kPinCacheBytes = size_t(2) << 30;
+constexpr size_t kPinCacheBytes = size_t(2) << 30;  // idle pinned buffers kept
 
-// Pinned host buffer of exactly `bytes`, reused from the pool when possible.
-void* pin_get(fftcg_server_s* srv, size_t bytes) {
+// Host buffer of exactly `bytes`: an idle pinned one from the pool, a new
+// pinned one, or (inputs only, once pin_input_cap bytes of pinned input
+// staging are in use: pinning costs about as much as the copy itself, and a
+// long queue need not hold pinned memory) pageable memory.
+void* pin_get(fftcg_server_s* srv, size_t bytes, bool input, bool* pinned) {
+    *pinned = true;
     {
         std::lock_guard<std::mutex> lk(srv->pin_mu);
         auto it = srv->pin_free.find(bytes);
@@ -443,18 +474,35 @@ void* pin_get(fftcg_server_s* srv, size_t bytes) {
             void* p = it->second;
             srv->pin_free.erase(it);
             srv->pin_cached -= bytes;
+            if (input) srv->pin_inputs += bytes;
             return p;
         }
+        if (input && srv->pin_inputs + bytes > srv->pin_input_cap) {
+            *pinned = false;
+            return malloc(bytes);
+        }
+        if (input) srv->pin_inputs += bytes;
     }
     void* p = nullptr;
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+        if (input) {
+            std::lock_guard<std::mutex> lk(srv->pin_mu);
+            srv->pin_inputs -= bytes;
+        }
+        return nullptr;
+    }
     return p;
 }
 
-void pin_put(fftcg_server_s* srv, void* p, size_t bytes) {
+void pin_put(fftcg_server_s* srv, void* p, size_t bytes, bool input, bool pinned) {
     if (!p) return;
+    if (!pinned) {
+        free(p);
+        return;
+    }
     {
         std::lock_guard<std::mutex> lk(srv->pin_mu);
+        if (input) srv->pin_inputs -= bytes;
         if (srv->pin_cached + bytes <= kPinCacheBytes) {
             srv->pin_free.emplace(bytes, p);
             srv->pin_cached += bytes;
@@ -465,9 +513,9 @@ void pin_put(fftcg_server_s* srv, void* p, size_t bytes) {
 }
 
 void free_request_buffers(fftcg_server_s* srv, Request* q) {
-    pin_put(srv, q->pin_in, q->n * 8 * 4);
-    pin_put(srv, q->pin_x, q->n * 8);
-    pin_put(srv, q->pin_broken, sizeof(int) * (size_t)q->steps);
+    pin_put(srv, q->pin_in, q->in_bytes, true, q->in_pinned);
+    pin_put(srv, q->pin_x, q->n * 8, false, true);
+    pin_put(srv, q->pin_broken, sizeof(int) * (size_t)q->steps, false, true);
     q->pin_in = q->pin_x = nullptr;
     q->pin_broken = nullptr;
 }
@@ -487,6 +535,7 @@ extern "C" int fftcg_server_create(const fftcg_server_opts* opts, fftcg_server_t
     if (s->opts.max_slots == 0) s->opts.max_slots = 64;
     if (s->opts.chunk_iters == 0) s->opts.chunk_iters = 10;
     if (s->opts.refresh_period == 0) s->opts.refresh_period = 50;
+    s->pin_input_cap = std::min(std::max(s->opts.memory_budget / 4, size_t(1) << 20), size_t(1) << 30);
     if (s->opts.queue_cap == 0) s->opts.queue_cap = 1 << 20;
     s->thread = std::thread(scheduler, s);
     *out = s;
@@ -520,17 +569,18 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     q->steps = steps;
     q->n = n;
     q->has_x0 = x0 != nullptr;
-    q->pin_in = (double*)pin_get(srv, n * 8 * 4);
-    q->pin_x = (double*)pin_get(srv, n * 8);
-    if (steps > 0) q->pin_broken = (int*)pin_get(srv, sizeof(int) * steps);
-    if (!q->pin_in || !q->pin_x || (steps > 0 && !q->pin_broken)) {
+    q->in_bytes = n * 8 * (2 + (x0 ? 1 : 0) + (t ? 1 : 0));
+    bool pinned = true;
+    q->pin_in = (double*)pin_get(srv, q->in_bytes, true, &q->in_pinned);
+    if (steps > 0) q->pin_broken = (int*)pin_get(srv, sizeof(int) * steps, false, &pinned);
+    if (!q->pin_in || (steps > 0 && !q->pin_broken)) {
         free_request_buffers(srv, q.get());
         return FFTCG_ENOMEM;
     }
     memcpy(q->pin_in, d, n * 8);
     memcpy(q->pin_in + n, b, n * 8);
     if (x0) memcpy(q->pin_in + 2 * n, x0, n * 8);
-    if (t) memcpy(q->pin_in + 3 * n, t, n * 8);
+    if (t) memcpy(q->pin_in + (x0 ? 3 : 2) * n, t, n * 8);
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->queued >= srv->opts.queue_cap) {
         free_request_buffers(srv, q.get());

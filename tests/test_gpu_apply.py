@@ -13,7 +13,7 @@ from gpu_util import dev, host, relerr, banner
 
 pytestmark = pytest.mark.gpu
 
-SMALL = [(L, p) for L in (2, 4, 8, 16, 32, 64, 128) for p in (0, 1)]
+SMALL = [(L, p) for L in (2, 4, 8, 16, 32, 64, 128) for p in (0, 1)] + [(256, 0)]
 
 
 def _inputs(L, padded, seed):
@@ -28,8 +28,8 @@ def _inputs(L, padded, seed):
 @pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS, binding.ENGINE_FUSED])
 def test_apply_small_direct(L, padded, engine):
     M = 2 * L if padded else L
-    if engine == binding.ENGINE_FUSED and M > 64:
-        pytest.skip("the fused engine serves M <= 64")
+    if engine == binding.ENGINE_FUSED and M > 256:
+        pytest.skip("the fused engine serves M <= 256")
     eps = 1e-3
     gh = spectrum(M, eps)
     g = kernel_table(gh)

@@ -45,12 +45,13 @@ def _wait(srv, tickets, L, timeout=120.0):
 
 @pytest.fixture(scope="module")
 def plans():
-    return {M: binding.Plan(M // 2, 1, spectrum(M, EPS)) for M in (32, 64, 128, 256)}
+    return {M: binding.Plan(M // 2, 1, spectrum(M, EPS)) for M in (32, 64, 128, 256, 512)}
 
 
 def test_alone_equals_mix(plans):
     banner("serve-alone-vs-mix")
-    reqs = [c4_request(k, M) for k, M in enumerate([64, 128, 64, 256, 32, 128, 64, 256])]
+    # M <= 256: fused classes (one workgroup per slot); M = 512: multi-pass
+    reqs = [c4_request(k, M) for k, M in enumerate([64, 128, 64, 256, 32, 128, 512, 64, 256, 512])]
     srv = binding.Server(memory_budget=1 << 30)
     alone = []
     for r in reqs:
@@ -117,6 +118,32 @@ def test_tight_budget_admission(plans):
     assert len(done) == len(tks)
     assert all(v.status == binding.OK for v in done.values())
     assert peak <= 2
+    srv.close()
+
+
+def test_pageable_inputs(plans):
+    """Past the pinned-staging cap (a quarter of the budget, at least 1 MiB)
+    queued inputs wait in pageable memory and reach the device through the
+    slot's staging buffer: results bitwise equal to pinned submissions."""
+    banner("serve-pageable")
+    reqs = [c4_request(400 + k, 128) for k in range(20)]  # 64 KiB of inputs each
+    ref = binding.Server(memory_budget=1 << 30)
+    want = []
+    for r in reqs:
+        st, tk = ref.submit(plans[128], r["d"], r["b"], tol=1e-8)
+        assert st == binding.OK
+        want.append(_wait(ref, [tk], 64)[tk].x)
+    ref.close()
+    srv = binding.Server(memory_budget=4 << 20, max_slots=2)
+    tks = []
+    for r in reqs:
+        st, tk = srv.submit(plans[128], r["d"], r["b"], tol=1e-8)
+        assert st == binding.OK
+        tks.append(tk)
+    res = _wait(srv, tks, 64)
+    for tk, w in zip(tks, want):
+        assert res[tk].status == binding.OK
+        assert np.array_equal(res[tk].x, w)
     srv.close()
 
 

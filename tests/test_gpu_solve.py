@@ -4,6 +4,8 @@
 * dense Cholesky on grids up to 16 x 16, periodic and padded, both modes;
 * periodic L = 64 instances (eps 1e-2) against the oracle's direct-route CG
   run to stagnation: relative error <= 1e-10 (FP64);
+* the serving grids on both engines: padded L = 32, 64, 128 (M <= 256) and
+  periodic L = 128, 256, against the oracle's direct-route CG, both modes;
 * padded L = 512 (eps 1e-3, 30% zeros in d) against the oracle's FFT-route
   reference: <= 1e-10 (FP64) and <= 1e-8 (mixed);
 * padded L = 2048 (eps 1e-4, b ~ N(0,1)) in mixed precision: the error is
@@ -82,6 +84,36 @@ def test_periodic_L64(s, engine):
           f"ms {info['device_ms']:.3f}")
     assert err <= 1e-10
     assert info["error_bound"] <= 1e-10
+
+
+_REFS = {}
+
+
+def _serving_reference(L, padded):
+    if (L, padded) not in _REFS:
+        inst = padded_instance(L, [63, L], eps=1e-3) if padded else periodic_instance(L, [64, L], eps=1e-2)
+        xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], padded, route="direct" if L <= 128 else "fft")
+        assert rinfo["bound"] < 1e-12
+        _REFS[(L, padded)] = (inst, xr)
+    return _REFS[(L, padded)]
+
+
+@pytest.mark.parametrize("L,padded", [(32, 1), (64, 1), (128, 1), (128, 0), (256, 0)])
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS, binding.ENGINE_FUSED])
+def test_serving_grids(L, padded, mode, engine):
+    prec, tol, bar = mode
+    inst, xr = _serving_reference(L, padded)
+    plan = binding.Plan(L, padded, inst["ghat"])
+    plan.set_engine(engine)
+    banner("serving-grid", L, padded, prec, engine)
+    x, info = _solve(plan, inst, prec, tol)
+    assert info["status"] == binding.OK, info
+    err = relerr(x, xr)
+    print(f"L {L} pad {padded} prec {prec} engine {engine}: iters {info['iterations']} checks {info['checks']} "
+          f"err {err:.3e} bound {info['error_bound']:.3e} ms {info['device_ms']:.3f}")
+    assert err <= bar
+    assert info["error_bound"] <= bar
 
 
 @pytest.fixture(scope="module")
