@@ -226,26 +226,29 @@ struct LdsLay {
     }
 };
 
-// v[r] *= w^(r m), r = 1..R-1, with w^m = tw[m] = exp(-2 pi i m / MTAB) (DIR
-// = -1) or its conjugate (DIR = +1).  Four table reads (m, 2m, 4m, 8m); the
-// other powers are products of at most three of them.
+// Twiddles of one radix-R butterfly: v[r] *= w^(r m), r = 1..R-1, with
+// w^m = tw[m] = exp(-2 pi i m / MTAB) (DIR = -1) or its conjugate (DIR = +1).
+// Four table reads (w^m, w^2m, w^4m, w^8m: the bases); the other powers are
+// products of at most three of them.  The bases of a stage are read before
+// the LDS exchange that precedes it, so their latency hides behind it.
+template <int R>
+__host__ __device__ constexpr int tw_nb() {
+    return R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1));
+}
+template <typename T, int R>
+__device__ __forceinline__ void tw_load(cx<T>* pb, const cx<T>* __restrict__ tw, int m) {
+    pb[0] = gld(tw + m);
+    if constexpr (R > 2) pb[1] = gld(tw + 2 * m);
+    if constexpr (R > 4) pb[2] = gld(tw + 4 * m);
+    if constexpr (R > 8) pb[3] = gld(tw + 8 * m);
+}
 template <typename T, int R, int DIR>
-__device__ __forceinline__ void twiddle_run(cx<T>* v, const cx<T>* __restrict__ tw, int m) {
-#ifdef FFTCG_TWIDDLE_DIRECT
-    // variant: one table read per power
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-        cx<T> w = gld(tw + r * m);
-        if (DIR > 0) w.y = -w.y;
-        v[r] = cmul(v[r], w);
-    }
-    return;
-#endif
+__device__ __forceinline__ void tw_apply(cx<T>* v, const cx<T>* pb) {
     cx<T> p[16];
-    p[1] = gld(tw + m);
-    if constexpr (R > 2) p[2] = gld(tw + 2 * m);
-    if constexpr (R > 4) p[4] = gld(tw + 4 * m);
-    if constexpr (R > 8) p[8] = gld(tw + 8 * m);
+    p[1] = pb[0];
+    if constexpr (R > 2) p[2] = pb[1];
+    if constexpr (R > 4) p[4] = pb[2];
+    if constexpr (R > 8) p[8] = pb[3];
     if constexpr (R > 3) p[3] = cmul(p[1], p[2]);
     if constexpr (R > 5) {
         p[5] = cmul(p[1], p[4]);
@@ -265,12 +268,13 @@ __device__ __forceinline__ void twiddle_run(cx<T>* v, const cx<T>* __restrict__ 
 }
 
 // Runs stages S.. of the length-N transform held by this thread (index j of
-// N/E threads).  On entry v[u R + r] holds position (j + u P) + r N / R_S.
-// On exit v[u R_last + r] holds position (j + u P) + r N / R_last.
+// N/E threads).  On entry v[u R + r] holds position (j + u P) + r N / R_S,
+// and pre holds the twiddle bases of stage S (if it has twiddles).  On exit
+// v[u R_last + r] holds position (j + u P) + r N / R_last.
 // tw[m] = exp(-2 pi i m / MTAB); DIR = -1 forward, +1 inverse.
 template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, int S, class Lay>
-__device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j,
-                                       const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j, const cx<T>* __restrict__ tw,
+                                       const cx<T>* pre) {
     constexpr int E = fft_elems(N);
     constexpr int P = N / E;
     constexpr int R = fft_radix(N, REV, S);
@@ -278,14 +282,20 @@ __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j,
     constexpr int NB = E / R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-        const int b = j + u * P;
-        if constexpr (NS > 1) {
-            constexpr int STEP = MTAB / (NS * R);
-            twiddle_run<T, R, DIR>(v + u * R, tw, (b & (NS - 1)) * STEP);
-        }
+        if constexpr (NS > 1) tw_apply<T, R, DIR>(v + u * R, pre + u * tw_nb<R>());
         dft<T, R, DIR, HALF_IN && S == 0>(v + u * R);
     }
     if constexpr (S + 1 < fft_nstages(N)) {
+        constexpr int R2 = fft_radix(N, REV, S + 1);
+        constexpr int NS2 = fft_ns(N, REV, S + 1);
+        constexpr int NB2 = E / R2;
+        cx<T> nxt[NB2 * tw_nb<R2>()];
+        if constexpr (NS2 > 1) {
+            constexpr int STEP2 = MTAB / (NS2 * R2);
+#pragma unroll
+            for (int u = 0; u < NB2; ++u)
+                tw_load<T, R2>(nxt + u * tw_nb<R2>(), tw, ((j + u * P) & (NS2 - 1)) * STEP2);
+        }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int b = j + u * P;
@@ -293,12 +303,10 @@ __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j,
             lay.template st_run<R, NS>(base, v + u * R);
         }
         __syncthreads();
-        constexpr int R2 = fft_radix(N, REV, S + 1);
-        constexpr int NB2 = E / R2;
 #pragma unroll
         for (int u = 0; u < NB2; ++u) lay.template ld_run<R2, N / R2>(j + u * P, v + u * R2);
         __syncthreads();
-        stages<T, N, MTAB, DIR, REV, HALF_IN, S + 1, Lay>(v, lay, j, tw);
+        stages<T, N, MTAB, DIR, REV, HALF_IN, S + 1, Lay>(v, lay, j, tw, nxt);
     }
 }
 
@@ -306,7 +314,8 @@ __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j,
 template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, class Lay>
 __device__ __forceinline__ void fft_run(cx<T>* v, const Lay& lay, int j,
                                         const cx<T>* __restrict__ tw) {
-    if constexpr (fft_nstages(N) > 0) stages<T, N, MTAB, DIR, REV, HALF_IN, 0, Lay>(v, lay, j, tw);
+    // stage 0 has no twiddles (NS = 1)
+    if constexpr (fft_nstages(N) > 0) stages<T, N, MTAB, DIR, REV, HALF_IN, 0, Lay>(v, lay, j, tw, nullptr);
 }
 
 // ---- reductions -----------------------------------------------------------

@@ -59,7 +59,10 @@ struct Geo {
     static constexpr int TT_fit(int t) {
         return (t > 1 && (t * M + (t * M) / 16 + t > COL_LDS_CAP || t * PC > 1024)) ? TT_fit(t / 2) : t;
     }
-    static constexpr int TT = TT_fit(cmin(N, 4));
+#ifndef FFTCG_COL_TTMAX
+#define FFTCG_COL_TTMAX 4
+#endif
+    static constexpr int TT = TT_fit(cmin(N, FFTCG_COL_TTMAX));
     static constexpr int COL_SH = ilog2c(16 * TT);
     static constexpr int COL_THREADS = TT * PC;
     static constexpr int NTILE = N / TT;
