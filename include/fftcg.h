@@ -125,11 +125,13 @@ int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* devi
 int fftcg_apply(fftcg_plan_t plan, int precision, const double* d,
                 const double* x, double* y, void* stream);
 
-/* fftcg_profile_apply -- measurement aid: runs `reps` operator products
- * exactly as fftcg_apply does, with HIP events on `stream` around each of
- * the three passes (row forward, column, row inverse), and stores the mean
- * device milliseconds of each pass in ms_per_pass[0..2] (HOST pointer).
- * Blocks until done.  FFTCG_EINVAL for the fused engine (one kernel).     */
+/* fftcg_profile_apply -- measurement aid: times each of the three passes
+ * of fftcg_apply (row forward, column, row inverse) with HIP events on
+ * `stream` around runs of 8 back-to-back launches of that pass, repeated
+ * ceil(reps / 8) times (every column run starts from a fresh row-forward
+ * output), and stores the mean device milliseconds per launch of each pass
+ * in ms_per_pass[0..2] (HOST pointer).  y is scratch (overwritten; not
+ * the product).  Blocks until done.  FFTCG_EINVAL for the fused engine.   */
 int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d,
                         const double* x, double* y, int reps,
                         double* ms_per_pass, void* stream);

@@ -47,7 +47,10 @@ struct Geo {
     static constexpr int PR = N / ER;
     static constexpr int ROW_WORDS = LdsLay<T, 1, 4, 1>::words(N);
     static constexpr int ROW_LDS_CAP = 73728 / (int)sizeof(cx<T>);  // two workgroups per CU
-    static constexpr int RPW0 = cmin(L, cmax(1, 256 / PR));
+#ifndef FFTCG_ROW_NT
+#define FFTCG_ROW_NT 256
+#endif
+    static constexpr int RPW0 = cmin(L, cmax(1, FFTCG_ROW_NT / PR));
     static constexpr int RPW_fit(int r) { return (r > 1 && r * ROW_WORDS > ROW_LDS_CAP) ? RPW_fit(r / 2) : r; }
     static constexpr int RPW = RPW_fit(RPW0);
     static constexpr int ROW_THREADS = RPW * PR;

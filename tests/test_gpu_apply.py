@@ -132,3 +132,20 @@ def test_stream_ordering_two_streams():
     torch.cuda.synchronize()
     for y in ys:
         assert relerr(host(y), ref) <= 1e-13
+
+
+def test_profile_apply():
+    """Per-pass timing aid: three positive times; the fused engine has no passes."""
+    L = 256
+    gh = spectrum(2 * L, 1e-3)
+    plan = binding.Plan(L, 1, gh)
+    d, x = _inputs(L, 1, 3)
+    banner("profile-apply", L)
+    y = dev(np.zeros((L, L)))
+    ms = plan.profile_apply(dev(d), dev(x), y, reps=9, precision=binding.MIXED)
+    assert len(ms) == 3 and all(np.isfinite(m) and m > 0 for m in ms)
+    small = binding.Plan(16, 1, spectrum(32, 1e-3))
+    small.set_engine(binding.ENGINE_FUSED)
+    d2, x2 = _inputs(16, 1, 4)
+    with pytest.raises(binding.FftcgError):
+        small.profile_apply(dev(d2), dev(x2), dev(np.zeros((16, 16))), reps=1)
