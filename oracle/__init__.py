@@ -25,6 +25,8 @@ Modules:
 * ``operator``     -- A x by the direct real-space sum, by an assembled
   dense matrix, and (for large grids) by numpy's FFT as a library step.
 * ``cg``           -- Hestenes-Stiefel CG in the order of Listing 2.
+* ``pcg``          -- CG with the Fourier-space (circulant) preconditioner
+  (an extension beyond the paper, which ran without one).
 * ``dense``        -- Cholesky solve of the assembled dense system.
 * ``bounds``       -- closed-form spectrum bounds and the certified stop rule.
 * ``loadstep``     -- the load-step rule of the load-stepped workload.
@@ -46,6 +48,7 @@ from .operator import (  # noqa: F401
     apply_fft,
 )
 from .cg import cg  # noqa: F401
+from .pcg import pcg, circulant_precond  # noqa: F401
 from .dense import solve_dense  # noqa: F401
 from .bounds import lambda_lb, lambda_ub, kappa_ub, certified_ok, error_bound  # noqa: F401
 from .loadstep import loadstep_argmax, loadstep_valid  # noqa: F401
