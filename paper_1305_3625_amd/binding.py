@@ -21,13 +21,14 @@ EINVAL, ENOMEM, ENOTSPD, ENOCONV, EBREAKDOWN = -1, -2, -3, -4, -5
 EAGAIN, EDEVICE, ENOTFOUND, ECANCELED = -6, -7, -8, -9
 FP64, MIXED = 0, 1
 ENGINE_AUTO, ENGINE_MULTIPASS, ENGINE_FUSED = 0, 1, 2
+PRECOND_NONE, PRECOND_CIRCULANT = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "ENOCONV",
                 -5: "EBREAKDOWN", -6: "EAGAIN", -7: "EDEVICE", -8: "ENOTFOUND", -9: "ECANCELED"}
 
 # every symbol include/fftcg.h declares
 EXPORTS = [
-    "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_info",
+    "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond", "fftcg_plan_info",
     "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_destroy",
@@ -93,6 +94,7 @@ def load(path: str = LIB_PATH):
         "fftcg_plan": (I, [I, I, P, ctypes.POINTER(P)]),
         "fftcg_plan_destroy": (I, [P]),
         "fftcg_plan_set_engine": (I, [P, I]),
+        "fftcg_plan_set_precond": (I, [P, I]),
         "fftcg_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                 ctypes.POINTER(S)]),
         "fftcg_apply": (I, [P, I, P, P, P, P]),
@@ -169,6 +171,11 @@ class Plan:
         st = load().fftcg_plan_set_engine(self.h, engine)
         if st != OK:
             raise FftcgError(st, "fftcg_plan_set_engine")
+
+    def set_precond(self, kind: int):
+        st = load().fftcg_plan_set_precond(self.h, kind)
+        if st != OK:
+            raise FftcgError(st, "fftcg_plan_set_precond")
 
     def info(self):
         L, M, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

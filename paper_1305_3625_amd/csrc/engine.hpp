@@ -36,6 +36,11 @@ struct EngineOps {
     // one FP64 check (row_fwd, col, row_inv on x, then the finaliser)
     void (*check)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
                   hipStream_t s);
+    // the same two for CG with the Fourier-space (circulant) preconditioner
+    void (*iter_pcg)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
+                     hipStream_t s);
+    void (*check_pcg)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
+                      hipStream_t s);
 };
 
 const EngineOps* find_engine(int M, int pad);

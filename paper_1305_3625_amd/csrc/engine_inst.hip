@@ -117,7 +117,7 @@ void check_t(const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, 
     hipLaunchKernelGGL((k_row_inv<double, M, PAD, EpiCheck<W>, ByPtr, RT>), dim3(G<double>::ROW_BLOCKS, nslots),
                        dim3(RT), 0, s, tab, sp, stride);
     hipLaunchKernelGGL((k_check_final<256>), dim3(1, nslots), dim3(256), 0, s, sp, G<double>::ROW_BLOCKS,
-                       g4_blocks(), stride);
+                       g4_blocks(), stride, LL * LL);
 }
 
 void check_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
@@ -125,6 +125,70 @@ void check_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, i
         check_t<double>(pt, slots, nslots, stride, s);
     else
         check_t<float>(pt, slots, nslots, stride, s);
+}
+
+// Preconditioned CG (Fourier-space circulant preconditioner): the operator
+// product with the direction (row_fwd with p = z + beta p, col, row_inv with
+// q and p.q), then r <- r - alpha q fused into the row-forward pass of the
+// preconditioner product (with r.r), its column pass with 1/(dbar + ghat),
+// and its row-inverse pass writing z and r.z.
+template <typename W, typename XA>
+void iter_pcg_t(const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS, RB = G<W>::ROW_BLOCKS;
+    const ByPtr sp{slots};
+    const Tab<W> tab = tab_of<W>(pt);
+    hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProPCG<W, XA, RT, RB>, ByPtr, RT>), dim3(RB, nslots), dim3(RT), 0, s,
+                       tab, sp, RB, stride);
+    hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE, nslots), dim3(CT), 0, s, tab,
+                       sp);
+    hipLaunchKernelGGL((k_row_inv<W, M, PAD, EpiCG<W>, ByPtr, RT>), dim3(RB, nslots), dim3(RT), 0, s, tab, sp,
+                       stride);
+    hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProUpdPre<W, RT, RB>, ByPtr, RT>), dim3(RB, nslots), dim3(RT), 0, s,
+                       tab, sp, 0, stride);
+    hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT, true>), dim3(G<W>::NTILE, nslots), dim3(CT), 0, s,
+                       tab, sp);
+    hipLaunchKernelGGL((k_row_inv<W, M, PAD, EpiPre<W, GateIter>, ByPtr, RT>), dim3(RB, nslots), dim3(RT), 0, s,
+                       tab, sp, stride);
+}
+
+void iter_pcg_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    if (prec == 0)
+        iter_pcg_t<double, double>(pt, slots, nslots, stride, s);
+    else
+        iter_pcg_t<float, float>(pt, slots, nslots, stride, s);
+}
+
+// FP64 check of the preconditioned solve (r.r partial count = the working
+// precision's row blocks), then z = P^{-1} r and r.z of the replaced
+// residual when the solve continues.
+template <typename W>
+void check_pcg_t(const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    constexpr int RT = G<double>::ROW_THREADS, CT = G<double>::COL_THREADS;
+    constexpr int RTW = G<W>::ROW_THREADS, CTW = G<W>::COL_THREADS, RBW = G<W>::ROW_BLOCKS;
+    const ByPtr sp{slots};
+    const Tab<double> tab = tab_of<double>(pt);
+    const Tab<W> tabw = tab_of<W>(pt);
+    hipLaunchKernelGGL((k_row_fwd<double, M, PAD, ProCheck<W, RT>, ByPtr, RT>),
+                       dim3(G<double>::ROW_BLOCKS, nslots), dim3(RT), 0, s, tab, sp, 0, stride);
+    hipLaunchKernelGGL((k_col<double, M, PAD, GateCheck, ByPtr, CT>), dim3(G<double>::NTILE, nslots), dim3(CT), 0,
+                       s, tab, sp);
+    hipLaunchKernelGGL((k_row_inv<double, M, PAD, EpiCheck<W>, ByPtr, RT>), dim3(G<double>::ROW_BLOCKS, nslots),
+                       dim3(RT), 0, s, tab, sp, stride);
+    hipLaunchKernelGGL((k_check_final<256>), dim3(1, nslots), dim3(256), 0, s, sp, G<double>::ROW_BLOCKS, RBW,
+                       stride, LL * LL);
+    hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProPre<W>, ByPtr, RTW>), dim3(RBW, nslots), dim3(RTW), 0, s, tabw, sp,
+                       0, stride);
+    hipLaunchKernelGGL((k_col<W, M, PAD, GatePre, ByPtr, CTW, true>), dim3(G<W>::NTILE, nslots), dim3(CTW), 0, s,
+                       tabw, sp);
+    hipLaunchKernelGGL((k_row_inv<W, M, PAD, EpiPre<W, GatePre>, ByPtr, RTW>), dim3(RBW, nslots), dim3(RTW), 0, s,
+                       tabw, sp, stride);
+}
+
+void check_pcg_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    if (prec == 0)
+        check_pcg_t<double>(pt, slots, nslots, stride, s);
+    else
+        check_pcg_t<float>(pt, slots, nslots, stride, s);
 }
 
 const EngineOps kOps = {M,
@@ -138,7 +202,9 @@ const EngineOps kOps = {M,
                         &apply_fn,
                         &apply_pass_fn,
                         &iter_fn,
-                        &check_fn};
+                        &check_fn,
+                        &iter_pcg_fn,
+                        &check_pcg_fn};
 
 }  // namespace
 

@@ -102,7 +102,7 @@ static int check_device() {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
-    void* dev[] = {W, r, p, q, e, d32, part, st, slot, ls_pv, ls_pi, ls_out};
+    void* dev[] = {W, r, p, q, z, e, d32, part, st, slot, ls_pv, ls_pi, ls_out};
     for (void* v : dev)
         if (v) (void)hipFree(v);
     if (h_slot) (void)hipHostFree(h_slot);
@@ -113,7 +113,7 @@ void Workspace::release() {
         if (ev[i]) (void)hipEventDestroy(ev[i]);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
-    W = r = p = q = nullptr;
+    W = r = p = q = z = nullptr;
     e = d32 = nullptr;
     part = nullptr;
     st = nullptr;
@@ -130,7 +130,7 @@ void Workspace::release() {
 size_t workspace_bytes(int L, int M, int stride) {
     const size_t n = (size_t)L * L;
     const size_t N = (size_t)M / 2;
-    return N * L * 16 + 3 * n * 8 + 2 * n * 4 + (size_t)NPART_SETS * stride * 8 + sizeof(SolveState) +
+    return N * L * 16 + 4 * n * 8 + 2 * n * 4 + (size_t)NPART_SETS * stride * 8 + sizeof(SolveState) +
            sizeof(SlotDesc) + 4096;
 }
 
@@ -144,6 +144,7 @@ int Workspace::init(int L_, int M_, int stride_) {
     HIPCHK(hipMalloc(&r, n * 8));
     HIPCHK(hipMalloc(&p, n * 8));
     HIPCHK(hipMalloc(&q, n * 8));
+    HIPCHK(hipMalloc(&z, n * 8));
     HIPCHK(hipMalloc((void**)&e, n * 4));
     HIPCHK(hipMalloc((void**)&d32, n * 4));
     HIPCHK(hipMalloc((void**)&part, (size_t)NPART_SETS * stride * 8));
@@ -313,6 +314,7 @@ extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) {
 // L = 128 on, the fused engine's serial rounds cost more than the launches
 // and the multi-pass engine takes over, for single solves and server classes.
 int fftcg::plan_engine(const fftcg_plan_s* p) {
+    if (p->precond != FFTCG_PRECOND_NONE) return FFTCG_ENGINE_MULTIPASS;  // the fused engine has no preconditioner
     if (p->engine == FFTCG_ENGINE_AUTO)
         return p->fused_ok && p->L <= 64 ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
     return p->engine;
@@ -337,6 +339,16 @@ extern "C" int fftcg_plan_set_engine(fftcg_plan_t plan, int engine) {
         return FFTCG_OK;
     }
     return FFTCG_EINVAL;
+}
+
+extern "C" int fftcg_plan_set_precond(fftcg_plan_t plan, int kind) {
+    if (!plan) return FFTCG_EINVAL;
+    if (kind != FFTCG_PRECOND_NONE && kind != FFTCG_PRECOND_CIRCULANT) return FFTCG_EINVAL;
+    if (kind == FFTCG_PRECOND_CIRCULANT && !plan->ops) return FFTCG_EINVAL;
+    if (plan->refs.load() > 0) return FFTCG_EINVAL;  // requests in a server use it
+    std::lock_guard<std::mutex> lk(plan->mu);
+    plan->precond = kind;
+    return FFTCG_OK;
 }
 
 extern "C" int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* device_bytes) {
@@ -455,6 +467,7 @@ void fftcg::init_state(SolveState* h, const fftcg_plan_s* p, int precision, doub
     // has fallen by 1e-2 since the last one (reliable updates)
     h->delta2 = precision == FFTCG_MIXED ? 1e-4 : 0.0;
     h->rho_ref = 0.0;
+    h->pcg = p->precond == FFTCG_PRECOND_CIRCULANT ? 1 : 0;
 }
 
 void fftcg::fill_slot(SlotDesc* h, const Workspace* w, double* x, const double* b, const double* d) {
@@ -465,6 +478,7 @@ void fftcg::fill_slot(SlotDesc* h, const Workspace* w, double* x, const double* 
     h->r = w->r;
     h->p = w->p;
     h->q = w->q;
+    h->z = w->z;
     h->e = w->e;
     h->d32 = w->d32;
     h->W = w->W;
@@ -531,14 +545,17 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
             rc = FFTCG_EDEVICE;
             break;
         }
-        ops->check(precision, plan->tabs, w->slot, 1, plan->stride, s);
+        const bool pcg = plan->precond == FFTCG_PRECOND_CIRCULANT;
+        const auto iter = pcg ? ops->iter_pcg : ops->iter;
+        const auto check = pcg ? ops->check_pcg : ops->check;
+        check(precision, plan->tabs, w->slot, 1, plan->stride, s);
         const int K = chunk_iters_for(plan->L);
         const long max_chunks = (long)maxit + 64;
         long c = 0;
         bool finished = false;
         while (!finished) {
-            for (int k = 0; k < K; ++k) ops->iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
-            ops->check(precision, plan->tabs, w->slot, 1, plan->stride, s);
+            for (int k = 0; k < K; ++k) iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
+            check(precision, plan->tabs, w->slot, 1, plan->stride, s);
             if (hipGetLastError() != hipSuccess || hipEventRecord(w->ev[c & 1], s) != hipSuccess) {
                 rc = FFTCG_EDEVICE;
                 break;

@@ -19,6 +19,7 @@ struct Workspace {
     void* r = nullptr;  // working vectors, L*L doubles each (FP32 uses half)
     void* p = nullptr;
     void* q = nullptr;
+    void* z = nullptr;     // preconditioned residual (preconditioned CG)
     float* e = nullptr;    // FP32 correction (mixed mode)
     float* d32 = nullptr;  // FP32 diagonal (mixed mode)
     double* part = nullptr;
@@ -57,6 +58,7 @@ struct FusedOps;
 struct fftcg_plan_s {
     int L = 0, M = 0, pad = 0, device = 0;
     int engine = FFTCG_ENGINE_AUTO;
+    int precond = FFTCG_PRECOND_NONE;
     int stride = 64;
     double gmin = 0, gmax = 0;
     const fftcg::EngineOps* ops = nullptr;

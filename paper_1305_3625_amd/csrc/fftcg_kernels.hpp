@@ -213,6 +213,11 @@ struct GateCheck {  // FP64 check kernels
         return sd.active && !sd.st->done && sd.st->pause;
     }
 };
+struct GatePre {  // preconditioner after a check that continues the solve
+    static __device__ __forceinline__ bool ok(const SlotDesc& sd) {
+        return sd.active && !sd.st->done && sd.st->need_pre;
+    }
+};
 
 template <typename T>
 struct Tab {
@@ -247,12 +252,12 @@ __device__ __forceinline__ cx<double> ld2f(const float* p) {
 // fftcg_apply: transform x (FP64 in memory), rounded to T.
 template <typename T>
 struct ProApply {
-    static constexpr int L_ = 0;
+    static constexpr int NACC = 0;
     struct Sh {};
     using Gate = GateAlways;
     static __device__ __forceinline__ bool begin(const SlotDesc&, Sh&, int, int) { return true; }
     template <int L>
-    static __device__ __forceinline__ cx<T> load2(const SlotDesc& sd, const Sh&, int row, int col) {
+    static __device__ __forceinline__ cx<T> load2(const SlotDesc& sd, const Sh&, int row, int col, double*) {
         cx<double> v = ld2<double>(sd.x + (size_t)row * L + col);
         return mkc((T)v.x, (T)v.y);
     }
@@ -263,6 +268,7 @@ struct ProApply {
 // W: working precision of r, p; XA: accumulator (double: x itself; float: e).
 template <typename W, typename XA, int NT>
 struct ProCG {
+    static constexpr int NACC = 0;
     struct Sh {
         double red[(NT + 63) / 64];
         W alpha, beta;
@@ -286,7 +292,7 @@ struct ProCG {
         return true;
     }
     template <int L>
-    static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col) {
+    static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col, double*) {
         const size_t idx = (size_t)row * L + col;
         W* p = reinterpret_cast<W*>(sd.p);
         const W* r = reinterpret_cast<const W*>(sd.r);
@@ -314,6 +320,7 @@ struct ProCG {
 // transform x in FP64.
 template <typename W, int NT>
 struct ProCheck {
+    static constexpr int NACC = 0;
     struct Sh {
         double alpha;
         int mixed;
@@ -326,7 +333,8 @@ struct ProCheck {
         return true;
     }
     template <int L>
-    static __device__ __forceinline__ cx<double> load2(const SlotDesc& sd, const Sh& sh, int row, int col) {
+    static __device__ __forceinline__ cx<double> load2(const SlotDesc& sd, const Sh& sh, int row, int col,
+                                                       double*) {
         const size_t idx = (size_t)row * L + col;
         cx<double> xv = ld2<double>(sd.x + idx);
         if (sh.mixed) {
@@ -343,6 +351,129 @@ struct ProCheck {
         }
         st2<double>(sd.x + idx, xv);
         return xv;
+    }
+};
+
+// Preconditioned CG (Fourier-space circulant preconditioner), first half of
+// an iteration: beta = (r.z) / (r.z)_old from the partials of the
+// preconditioner pass, p = z + beta p (p = z on restart), pending x update,
+// then transform p.  The stop triggers still use r.r.  NPZ: partial count of
+// the r.z sums.
+template <typename W, typename XA, int NT, int NPZ>
+struct ProPCG {
+    static constexpr int NACC = 0;
+    struct Sh {
+        double red[(NT + 63) / 64];
+        W alpha, beta;
+        int restart;
+    };
+    using Gate = GateIter;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd, Sh& sh, int npart_rr, int stride) {
+        if (!GateIter::ok(sd)) return false;
+        SolveState* st = sd.st;
+        const double rr = sum_partials<NT>(sd.part + PS_RR * stride, npart_rr, sh.red);
+        if (check_due(st, rr)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) st->pause = 1;
+            return false;
+        }
+        const double rz = sum_partials<NT>(sd.part + PS_RZ * stride, NPZ, sh.red);
+        const int restart = st->restart;
+        const double beta = restart ? 0.0 : rz / st->rho_prev;
+        sh.alpha = (W)st->alpha;
+        sh.beta = (W)beta;
+        sh.restart = restart;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->rho_cur = rz;
+            st->need_pre = 0;
+        }
+        return true;
+    }
+    template <int L>
+    static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col, double*) {
+        const size_t idx = (size_t)row * L + col;
+        W* p = reinterpret_cast<W*>(sd.p);
+        const W* z = reinterpret_cast<const W*>(sd.z);
+        cx<W> z2 = ld2<W>(z + idx);
+        cx<W> p2;
+        if (sh.restart) {
+            p2 = z2;
+        } else {
+            cx<W> po = ld2<W>(p + idx);
+            p2 = mkc(z2.x + sh.beta * po.x, z2.y + sh.beta * po.y);
+            if (sh.alpha != W(0)) {
+                XA* xa = reinterpret_cast<XA*>(sizeof(XA) == 8 ? (void*)sd.x : (void*)sd.e);
+                cx<XA> xv = ld2<XA>(xa + idx);
+                xv.x += (XA)sh.alpha * (XA)po.x;
+                xv.y += (XA)sh.alpha * (XA)po.y;
+                st2<XA>(xa + idx, xv);
+            }
+        }
+        st2<W>(p + idx, p2);
+        return p2;
+    }
+};
+
+// Preconditioned CG, second half: alpha = (r.z) / (p.q) from the partials of
+// the operator's row-inverse pass (breakdown if p.q <= 0), r <- r - alpha q
+// with partial r.r, then transform r for z = P^{-1} r.  NPQ: partial count of
+// the p.q sums.
+template <typename W, int NT, int NPQ>
+struct ProUpdPre {
+    static constexpr int NACC = 1;
+    static constexpr int SET = PS_RR;
+    struct Sh {
+        double red[(NT + 63) / 64];
+        W alpha;
+    };
+    using Gate = GateIter;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd, Sh& sh, int, int stride) {
+        if (!GateIter::ok(sd)) return false;
+        SolveState* st = sd.st;
+        const double pq = sum_partials<NT>(sd.part + PS_PQ * stride, NPQ, sh.red);
+        const double rho = st->rho_cur;
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->status = ST_EBREAKDOWN;
+                st->done = 1;
+                publish_status(sd, 1, ST_EBREAKDOWN, st->gen, st->iters);
+            }
+            return false;
+        }
+        const double alpha = rho / pq;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->alpha = alpha;
+            st->rho_prev = rho;
+            st->iters += 1;
+            st->restart = 0;
+        }
+        sh.alpha = (W)alpha;
+        return true;
+    }
+    template <int L>
+    static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col,
+                                                  double* acc) {
+        const size_t idx = (size_t)row * L + col;
+        W* r = reinterpret_cast<W*>(sd.r);
+        const W* q = reinterpret_cast<const W*>(sd.q);
+        const cx<W> r2 = ld2<W>(r + idx), q2 = ld2<W>(q + idx);
+        const cx<W> rn = mkc(r2.x - sh.alpha * q2.x, r2.y - sh.alpha * q2.y);
+        st2<W>(r + idx, rn);
+        acc[0] += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
+        return rn;
+    }
+};
+
+// Preconditioner after a check that continues the solve: transform the
+// replaced residual r.
+template <typename W>
+struct ProPre {
+    static constexpr int NACC = 0;
+    struct Sh {};
+    using Gate = GatePre;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd, Sh&, int, int) { return GatePre::ok(sd); }
+    template <int L>
+    static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh&, int row, int col, double*) {
+        return ld2<W>(reinterpret_cast<const W*>(sd.r) + (size_t)row * L + col);
     }
 };
 
@@ -368,6 +499,7 @@ struct EpiApply {
 template <typename W>
 struct EpiCG {
     static constexpr int NACC = 1;
+    static constexpr int SET = PS_PQ;
     using Gate = GateIter;
     static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return GateIter::ok(sd); }
     template <int L>
@@ -393,7 +525,7 @@ struct EpiCG {
 // |r64 - r_old|^2 (drift of the recursive residual it replaces).
 template <typename W>
 struct EpiCheck {
-    static constexpr int NACC = 7;
+    static constexpr int NACC = 8;
     using Gate = GateCheck;
     static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return GateCheck::ok(sd); }
     template <int L>
@@ -420,6 +552,24 @@ struct EpiCheck {
         const bool ok = isfinite(bv.x) && isfinite(bv.y) && isfinite(dv.x) && isfinite(dv.y) &&
                         dv.x >= 0.0 && dv.y >= 0.0;
         acc[5] += ok ? 0.0 : 1.0;
+        acc[7] += dv.x + dv.y;
+    }
+};
+
+// Preconditioner: z = C' r (C' the convolution with 1/(dbar + ghat); no
+// diagonal term); partial r . z (FP64 accumulation).
+template <typename W, class G>
+struct EpiPre {
+    static constexpr int NACC = 1;
+    static constexpr int SET = PS_RZ;
+    using Gate = G;
+    static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return G::ok(sd); }
+    template <int L>
+    static __device__ __forceinline__ void out2(const SlotDesc& sd, int row, int col, W c0, W c1, double* acc) {
+        const size_t idx = (size_t)row * L + col;
+        const cx<W> rv = ld2<W>(reinterpret_cast<const W*>(sd.r) + idx);
+        st2<W>(reinterpret_cast<W*>(sd.z) + idx, mkc(c0, c1));
+        acc[0] += (double)rv.x * (double)c0 + (double)rv.y * (double)c1;
     }
 };
 
@@ -433,8 +583,10 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     static_assert(NT == G::ROW_THREADS, "row-forward block size");
     __shared__ cx<T> lds[RPW * WORDS];
     __shared__ typename Pro::Sh sh;
+    __shared__ double fred[(NT + 63) / 64];
     const SlotDesc& sd = slot.get();
     if (!Pro::begin(sd, sh, npart_rr, stride)) return;
+    double acc = 0.0;
     const int tid = threadIdx.x;
     const int rl = tid / P, j = tid % P;
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
@@ -449,7 +601,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
         for (int r = 0; r < R1; ++r) {
             if (PAD && r >= R1 / 2) continue;  // known zeros (padded grid)
             const int n = (j + u * P) + r * (N / R1);
-            v[u * R1 + r] = Pro::template load2<L>(sd, sh, row, 2 * n);
+            v[u * R1 + r] = Pro::template load2<L>(sd, sh, row, 2 * n, &acc);
         }
     }
     fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
@@ -478,9 +630,22 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
         }
         gst(Wb + ((size_t)kt * L + rb * RPW + il) * TT + kk, out);
     }
+    if constexpr (Pro::NACC > 0) {
+        const double s = block_sum<NT>(acc, fred);
+        if (tid == 0) sd.part[Pro::SET * stride + blockIdx.x] = s;
+    }
 }
 
-template <typename T, int M, int PAD, class Gate, class Slot, int NT>
+// Multiplier of the preconditioner from the stored ghat / M^2:
+// 1 / (M^2 (dbar + ghat)) = 1 / (M^2 dbar + M^4 g).  Real, positive and even
+// like ghat, so the preconditioner is symmetric positive definite.
+__device__ __forceinline__ float pre_mul(float g, float c2, float c4) {
+    return __builtin_amdgcn_rcpf(fmaf(c4, g, c2));
+}
+__device__ __forceinline__ double pre_mul(double g, double c2, double c4) { return 1.0 / fma(c4, g, c2); }
+
+// PRE: multiply by the preconditioner's multiplier instead of ghat / M^2.
+template <typename T, int M, int PAD, class Gate, class Slot, int NT, bool PRE = false>
 __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
     using G = Geo<T, M, PAD>;
     constexpr int E = G::EC, P = G::PC, TT = G::TT, L = G::L, MH = G::MH;
@@ -517,6 +682,12 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
             const int mp = m <= M - m ? m : M - m;
             gpre[u * RL + r] = g[mp * TT + kk];
         }
+    const T c2 = PRE ? (T)((double)M * (double)M * sd.st->dbar) : T(0);
+    const T c4 = (T)((double)M * (double)M * (double)M * (double)M);
+    if constexpr (PRE) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) gpre[i] = pre_mul(gpre[i], c2, c4);
+    }
     fft_run<T, M, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
     if (kt == 0) {
         // packed column 0 carries k = 0 (real part) and k = M/2 (imaginary
@@ -534,7 +705,8 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
                 const cx<T> a = v[u * RL + r];
                 if (kk == 0) {
                     const cx<T> bm = conjc(lay.ld((M - m) & (M - 1)));
-                    const T g0 = gpre[u * RL + r], gN = tab.ghN[mp];
+                    const T g0 = gpre[u * RL + r];
+                    const T gN = PRE ? pre_mul(tab.ghN[mp], c2, c4) : tab.ghN[mp];
                     const T s = T(0.5) * (g0 + gN), t = T(0.5) * (g0 - gN);
                     v[u * RL + r] = mkc(s * a.x + t * bm.x, s * a.y + t * bm.y);
                 } else {
@@ -637,11 +809,12 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
         double* part = sd.part;
         if constexpr (Epi::NACC == 1) {
             const double s = block_sum<NT>(acc[0], red);
-            if (tid == 0) part[PS_PQ * stride + blockIdx.x] = s;
+            if (tid == 0) part[Epi::SET * stride + blockIdx.x] = s;
         } else {
-            const int sets[7] = {PS_CHK_R, PS_CHK_X, PS_CHK_B, PS_CHK_RW, PS_CHK_DMIN, PS_CHK_BAD, PS_CHK_DIFF};
+            const int sets[8] = {PS_CHK_R,    PS_CHK_X,   PS_CHK_B,    PS_CHK_RW,
+                                 PS_CHK_DMIN, PS_CHK_BAD, PS_CHK_DIFF, PS_CHK_DSUM};
 #pragma unroll
-            for (int a = 0; a < 7; ++a) {
+            for (int a = 0; a < 8; ++a) {
                 const double s = (a == 4) ? block_min<NT>(acc[a], red) : block_sum<NT>(acc[a], red);
                 if (tid == 0) part[sets[a] * stride + blockIdx.x] = s;
             }
@@ -723,7 +896,7 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
 // Single-block finaliser of an FP64 check: stop decision, residual
 // replacement, restart guard, and status for the host.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, int npart_rr, int stride) {
+__global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, int npart_rr, int stride, int n) {
     __shared__ double red[(NT + 63) / 64];
     __shared__ int s_update;
     const SlotDesc& sd = slot.get();
@@ -740,11 +913,15 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
     const double RW = sum_partials<NT>(part + PS_CHK_RW * stride, npart_chk, red);
     const double BAD = sum_partials<NT>(part + PS_CHK_BAD * stride, npart_chk, red);
     const double DIFF = sum_partials<NT>(part + PS_CHK_DIFF * stride, npart_chk, red);
+    const double DSUM = sum_partials<NT>(part + PS_CHK_DSUM * stride, npart_chk, red);
     double dmin = 1.0e300;
     for (int i = threadIdx.x; i < npart_chk; i += NT) dmin = fmin(dmin, part[PS_CHK_DMIN * stride + i]);
     dmin = block_min<NT>(dmin, red);
     if (threadIdx.x == 0) {
+        if (st->checks == 0) st->dbar = DSUM / (double)n;
         s_update = check_decide(st, R, X, B, RW, BAD, DIFF, dmin);
+        // preconditioned CG: z = P^{-1} r of the replaced residual comes next
+        st->need_pre = (s_update && st->pcg) ? 1 : 0;
         publish_status(sd, st->done, st->status, st->gen, st->iters);
     }
     __syncthreads();

@@ -15,8 +15,8 @@ namespace fftcg {
 // check finaliser), and no other block of that launch reads it, so no
 // intra-launch synchronisation is needed.
 struct SolveState {
-    double rho_cur;      // r_k . r_k            (row-forward kernel, block 0)
-    double rho_prev;     // r_{k-1} . r_{k-1}    (update kernel, block 0)
+    double rho_cur;      // r_k . r_k (r_k . z_k preconditioned)  (row-forward kernel, block 0)
+    double rho_prev;     // the same for k - 1                    (update kernel, block 0)
     double alpha;        // alpha of the last iteration whose x update is pending
     double tol;          // residual rule ||r||/||b|| <= tol
     double tau;          // certified error target
@@ -31,6 +31,7 @@ struct SolveState {
     double best_rt;      // smallest true residual seen
     double rho_ref;      // r.r right after the last check (residual replacement)
     double delta2;       // reliable-update threshold: check when r.r <= delta2 * rho_ref
+    double dbar;         // mean of d (first check), for the preconditioner
     int iters;           // CG iterations done
     int maxit;
     int refresh;         // FP64 check period (0 = only at candidate convergence)
@@ -45,6 +46,8 @@ struct SolveState {
     int bzero;           // b == 0 detected
     int mixed;           // 1: working vectors are FP32
     int gen;             // generation of this solve (published with the status)
+    int pcg;             // 1: Fourier-space (circulant) preconditioned CG
+    int need_pre;        // 1: z = P^{-1} r is due after a check (check finaliser)
 };
 
 // Per-slot descriptor (device memory).
@@ -56,6 +59,7 @@ struct SlotDesc {
     void* r;             // residual           (working precision)
     void* p;             // search direction   (working precision)
     void* q;             // A p                (working precision)
+    void* z;             // preconditioned residual (working precision)
     float* e;            // FP32 correction accumulated since the last check
     float* d32;          // FP32 copy of d (mixed mode)
     void* W;             // FFT workspace (pruned half spectrum, in place)
@@ -77,7 +81,9 @@ enum PartSet {
     PS_CHK_DMIN = 6,  // min d
     PS_CHK_BAD = 7,   // count of non-finite / negative inputs
     PS_CHK_DIFF = 8,  // |r64 - r_recursive|^2: drift of the recursive residual
-    NPART_SETS = 9
+    PS_RZ = 9,        // r . z per block of the preconditioner's row-inverse pass
+    PS_CHK_DSUM = 10, // sum of d (for its mean)
+    NPART_SETS = 11
 };
 
 }  // namespace fftcg

@@ -419,9 +419,12 @@ bool progress(fftcg_server_s* srv, Class* c) {
             fused_launch(c->plan, c->precision, c->d_table, nsl, srv->opts.chunk_iters, c->stream);
         } else {
             const EngineOps* ops = c->plan->ops;
+            const bool pcg = c->plan->precond == FFTCG_PRECOND_CIRCULANT;
+            const auto iter = pcg ? ops->iter_pcg : ops->iter;
+            const auto check = pcg ? ops->check_pcg : ops->check;
             for (int k = 0; k < srv->opts.chunk_iters; ++k)
-                ops->iter(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
-            ops->check(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+                iter(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+            check(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
         }
         (void)hipEventRecord(c->ev[c->next_ev], c->stream);
         c->next_ev ^= 1;
