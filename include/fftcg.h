@@ -120,6 +120,19 @@ typedef struct {
  * stored spectrum.  The plan owns its device memory (current device).       */
 int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftcg_plan_t* out);
 
+/* fftcg_greens_spectrum -- the spectrum of the physical Green's function of
+ * Sec. 2, eq. (1c): G(Delta) = (1 - nu^2)/(pi E a) * P(Delta), P the
+ * integral of 1/r over the unit square centred at the lattice separation
+ * Delta (the 1/r kernel averaged over the source fibre's plaquette, lengths
+ * in units of a), tabulated on the M x M grid (M = padded ? 2L : L) at
+ * separations min(i, M - i) per index, and transformed by a DFT.  Writes the
+ * real, even, positive spectrum to `spectrum` (HOST pointer, M*M doubles,
+ * [m*M + n]), ready for fftcg_plan.  Host computation (plan time); no GPU.
+ * FFTCG_EINVAL unless L is a power of two in [2, 2048], E > 0, a > 0 and
+ * |nu| < 1 (all finite).  With uniform fibre stiffness k the system of
+ * eq. (2) divided by k is diag(1/k) + C with this spectrum.               */
+int fftcg_greens_spectrum(int L, int padded, double nu, double E, double a, double* spectrum);
+
 /* Releases the plan.  FFTCG_EINVAL if a server still holds requests on it.  */
 int fftcg_plan_destroy(fftcg_plan_t plan);
 

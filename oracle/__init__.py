@@ -28,6 +28,8 @@ Modules:
 * ``pcg``          -- CG with the Fourier-space (circulant) preconditioner
   (an extension beyond the paper, which ran without one).
 * ``dense``        -- Cholesky solve of the assembled dense system.
+* ``greens``       -- the physical Green's function of eq. (1c) and its
+  spectrum (plaquette-averaged 1/r kernel, closed form).
 * ``bounds``       -- closed-form spectrum bounds and the certified stop rule.
 * ``loadstep``     -- the load-step rule of the load-stepped workload.
 * ``reference``    -- reference solves run to stagnation and certified.
@@ -50,6 +52,7 @@ from .operator import (  # noqa: F401
 from .cg import cg  # noqa: F401
 from .pcg import pcg, circulant_precond  # noqa: F401
 from .dense import solve_dense  # noqa: F401
+from .greens import plaquette_integral, green_table, green_spectrum  # noqa: F401
 from .bounds import lambda_lb, lambda_ub, kappa_ub, certified_ok, error_bound  # noqa: F401
 from .loadstep import loadstep_argmax, loadstep_valid  # noqa: F401
 from .reference import reference_solve  # noqa: F401

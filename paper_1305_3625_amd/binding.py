@@ -32,7 +32,7 @@ EXPORTS = [
     "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_destroy",
-    "fftcg_strerror", "fftcg_version",
+    "fftcg_strerror", "fftcg_version", "fftcg_greens_spectrum",
 ]
 
 
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
         "fftcg_server_destroy": (I, [P]),
         "fftcg_strerror": (ctypes.c_char_p, [I]),
         "fftcg_version": (ctypes.c_char_p, []),
+        "fftcg_greens_spectrum": (I, [I, I, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -118,6 +119,19 @@ def load(path: str = LIB_PATH):
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def greens_spectrum(L, padded, nu, E, a):
+    """fftcg_greens_spectrum: spectrum of the Green's function of eq. (1c) on
+    the M x M grid (numpy array)."""
+    import numpy as np
+    M = 2 * L if padded else L
+    out = np.empty((M, M))
+    st = load().fftcg_greens_spectrum(int(L), int(padded), float(nu), float(E), float(a),
+                                      out.ctypes.data_as(ctypes.c_void_p))
+    if st != OK:
+        raise FftcgError(st, "fftcg_greens_spectrum")
+    return out
 
 
 def strerror(status: int) -> str:

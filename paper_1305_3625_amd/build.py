@@ -40,7 +40,7 @@ ENGINE_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048,
 
 FUSED_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256)] + [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256)]
 
-SOURCES = ["fftcg_host.cpp", "common.hip", "fused.hip", "server.cpp"]
+SOURCES = ["fftcg_host.cpp", "common.hip", "fused.hip", "server.cpp", "greens.cpp"]
 
 
 def _run(cmd):
