@@ -106,7 +106,8 @@ typedef struct {
 } fftcg_info;
 
 /* fftcg_plan -- build the spectral operator for one grid.
- *   L               grid side, power of two, 2 <= L <= 2048.
+ *   L               grid side, power of two, L >= 2, M <= 8192 (L <= 4096
+ *                   padded, L <= 8192 periodic).
  *   padded          0: periodic grid, M = L.  1: zero-padded, M = 2L.
  *   kernel_spectrum HOST pointer to M*M doubles, ghat[m*M + n] (m along the
  *                   row index).  Copied; the caller keeps ownership.
@@ -128,7 +129,7 @@ int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftcg_plan_t* o
  * separations min(i, M - i) per index, and transformed by a DFT.  Writes the
  * real, even, positive spectrum to `spectrum` (HOST pointer, M*M doubles,
  * [m*M + n]), ready for fftcg_plan.  Host computation (plan time); no GPU.
- * FFTCG_EINVAL unless L is a power of two in [2, 2048], E > 0, a > 0 and
+ * FFTCG_EINVAL unless L is a power of two with 2 <= L and M <= 8192, E > 0, a > 0 and
  * |nu| < 1 (all finite).  With uniform fibre stiffness k the system of
  * eq. (2) divided by k is diag(1/k) + C with this spectrum.               */
 int fftcg_greens_spectrum(int L, int padded, double nu, double E, double a, double* spectrum);

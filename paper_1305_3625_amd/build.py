@@ -35,8 +35,8 @@ CXXFLAGS = [
     f"-I{INC}", f"-I{CSRC}",
 ]
 
-ENGINE_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)] + \
-               [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)]
+ENGINE_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)] + \
+               [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)]
 
 FUSED_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256)] + [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256)]
 

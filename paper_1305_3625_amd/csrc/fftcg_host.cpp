@@ -31,8 +31,8 @@ namespace fftcg {
 #define FFTCG_DECL(M, P) const EngineOps* fftcg_engine_ops_##M##_##P();
 #define FFTCG_SIZES(X)                                                                          \
     X(2, 0) X(4, 0) X(8, 0) X(16, 0) X(32, 0) X(64, 0) X(128, 0) X(256, 0) X(512, 0) X(1024, 0) \
-        X(2048, 0) X(4096, 0) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(128, 1) X(256, 1)    \
-            X(512, 1) X(1024, 1) X(2048, 1) X(4096, 1)
+        X(2048, 0) X(4096, 0) X(8192, 0) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(128, 1)    \
+            X(256, 1) X(512, 1) X(1024, 1) X(2048, 1) X(4096, 1) X(8192, 1)
 FFTCG_SIZES(FFTCG_DECL)
 #undef FFTCG_DECL
 
@@ -217,8 +217,8 @@ fftcg_plan_s::~fftcg_plan_s() {
 }
 
 int fftcg::plan_validate(int L, int padded, const double* g, double* gmin_out, double* gmax_out) {
-    if (!ispow2(L) || L < 2 || L > 2048) return FFTCG_EINVAL;
     if (padded != 0 && padded != 1) return FFTCG_EINVAL;
+    if (!ispow2(L) || L < 2 || (padded ? 2 * L : L) > 8192) return FFTCG_EINVAL;
     if (!g) return FFTCG_EINVAL;
     const int M = padded ? 2 * L : L;
     double gmin = INFINITY, gmax = 0.0;

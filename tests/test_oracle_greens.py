@@ -86,6 +86,6 @@ def test_library_spectrum_matches_oracle(L, padded):
 def test_library_spectrum_errors():
     from paper_1305_3625_amd import binding
     for args in [(3, 1, 0.3, 1.0, 1.0), (16, 1, 1.0, 1.0, 1.0), (16, 1, 0.3, 0.0, 1.0), (16, 1, 0.3, 1.0, -1.0),
-                 (4096, 1, 0.3, 1.0, 1.0), (16, 2, 0.3, 1.0, 1.0)]:
+                 (8192, 1, 0.3, 1.0, 1.0), (16, 2, 0.3, 1.0, 1.0)]:
         with pytest.raises(binding.FftcgError):
             binding.greens_spectrum(*args)
