@@ -201,6 +201,29 @@ int fftcg_solve(fftcg_plan_t plan, int precision, const double* d,
 int fftcg_loadstep(fftcg_plan_t plan, const double* x, const double* t,
                    double* d, int* index, void* stream);
 
+/* fftcg_fracture -- the quasi-static fracture driver of Sec. 2: uniform
+ * fibre stiffness k (> 0), displacement control, fibres breaking one at a
+ * time.  Each step solves, at unit displacement, (I/k + G)_II f_I = 1_I on
+ * the intact fibres I (eq. (2) divided by k; broken fibres carry no force and
+ * are projected out of the solve), to the relative error tol (certified as
+ * for fftcg_solve, `precision` as there), warm-started from the previous
+ * step; then the intact fibre with the largest f_i / t_i breaks (ties to the
+ * smallest row-major index), at the displacement D = t_i / f_i.
+ *   t        DEVICE pointer, L*L thresholds (> 0; a gradient across the grid
+ *            directs the front, Sec. 2).
+ *   steps    number of fibres to break, 1 <= steps <= L*L.
+ *   f        DEVICE pointer, L*L doubles: forces at unit displacement of the
+ *            last step's intact set (zero on broken fibres).
+ *   broken   HOST, steps ints: the fibre broken at each step.
+ *   dbreak   HOST, steps doubles: the displacement at which it breaks
+ *            (+inf if no intact fibre carries a positive force).
+ *   iters    HOST, steps ints, or NULL: CG iterations of each step's solve.
+ * Multi-pass engine (the plan's preconditioner setting applies).  Blocks
+ * until done; the first failing solve's status is returned (FFTCG_ENOCONV
+ * included) with the steps done so far written.                           */
+int fftcg_fracture(fftcg_plan_t plan, int precision, double k, const double* t, int steps, double tol,
+                   int maxit, double* f, int* broken, double* dbreak, int* iters, void* stream);
+
 /* ---- continuous-batching server ---------------------------------------- */
 typedef struct {
     size_t memory_budget;     /* bytes of device memory for request slots   */

@@ -32,6 +32,8 @@ Modules:
   spectrum (plaquette-averaged 1/r kernel, closed form).
 * ``bounds``       -- closed-form spectrum bounds and the certified stop rule.
 * ``loadstep``     -- the load-step rule of the load-stepped workload.
+* ``fracture``     -- the quasi-static fracture driver of Sec. 2 (restricted
+  solves with broken fibres projected out).
 * ``reference``    -- reference solves run to stagnation and certified.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
@@ -55,4 +57,5 @@ from .dense import solve_dense  # noqa: F401
 from .greens import plaquette_integral, green_table, green_spectrum  # noqa: F401
 from .bounds import lambda_lb, lambda_ub, kappa_ub, certified_ok, error_bound  # noqa: F401
 from .loadstep import loadstep_argmax, loadstep_valid  # noqa: F401
+from .fracture import restricted_solve, fracture_sequence  # noqa: F401
 from .reference import reference_solve  # noqa: F401

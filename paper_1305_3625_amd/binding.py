@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD"
 # every symbol include/fftcg.h declares
 EXPORTS = [
     "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond", "fftcg_plan_info",
-    "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep",
+    "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep", "fftcg_fracture",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_destroy",
     "fftcg_strerror", "fftcg_version", "fftcg_greens_spectrum",
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
         "fftcg_server_completed": (I, [P, ctypes.POINTER(ctypes.c_uint64), I, ctypes.POINTER(I)]),
         "fftcg_server_get_stats": (I, [P, ctypes.POINTER(ServerStats)]),
         "fftcg_server_destroy": (I, [P]),
+        "fftcg_fracture": (I, [P, I, ctypes.c_double, P, I, ctypes.c_double, I, P, P, P, P, P]),
         "fftcg_strerror": (ctypes.c_char_p, [I]),
         "fftcg_version": (ctypes.c_char_p, []),
         "fftcg_greens_spectrum": (I, [I, I, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]),
@@ -198,6 +199,17 @@ class Plan:
         if st != OK:
             raise FftcgError(st, "fftcg_plan_info")
         return dict(L=L.value, M=M.value, padded=p.value, device_bytes=b.value)
+
+    def fracture(self, k, t, f, steps, tol=1e-8, maxit=10000, precision=MIXED, stream=None):
+        """fftcg_fracture: returns (status, broken, dbreak, iters) host arrays."""
+        import numpy as np
+        broken = np.zeros(steps, dtype=np.int32)
+        dbreak = np.zeros(steps)
+        iters = np.zeros(steps, dtype=np.int32)
+        st = load().fftcg_fracture(self.h, precision, float(k), _ptr(t), int(steps), float(tol), int(maxit), _ptr(f),
+                                   broken.ctypes.data_as(ctypes.c_void_p), dbreak.ctypes.data_as(ctypes.c_void_p),
+                                   iters.ctypes.data_as(ctypes.c_void_p), _stream(stream))
+        return st, broken, dbreak, iters
 
     def close(self):
         if getattr(self, "h", None) is not None:

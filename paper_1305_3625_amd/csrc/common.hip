@@ -51,12 +51,16 @@ __device__ VI block_best(VI a) {
     return r;
 }
 
+// Entries whose marker is 0 are excluded: d == 0 (load-stepped sequences:
+// the broken bond has no diagonal term left) or mask == 0 (fracture driver:
+// the broken fibre is projected out).
+template <typename MK>
 __global__ void __launch_bounds__(LS_NT)
-    k_loadstep_partial(const double* __restrict__ x, const double* __restrict__ t,
-                       const double* __restrict__ d, int n, double* __restrict__ pv, int* __restrict__ pi) {
+    k_loadstep_partial(const double* __restrict__ x, const double* __restrict__ t, const MK* __restrict__ mk,
+                       int n, double* __restrict__ pv, int* __restrict__ pi) {
     VI best{-INFINITY, n};
     for (int i = blockIdx.x * LS_NT + threadIdx.x; i < n; i += gridDim.x * LS_NT) {
-        if (d[i] != 0.0) best = better(best, VI{x[i] / t[i], i});
+        if (mk[i] != MK(0)) best = better(best, VI{x[i] / t[i], i});
     }
     best = block_best(best);
     if (threadIdx.x == 0) {
@@ -65,16 +69,18 @@ __global__ void __launch_bounds__(LS_NT)
     }
 }
 
+template <typename MK>
 __global__ void __launch_bounds__(LS_NT)
     k_loadstep_final(const double* __restrict__ pv, const int* __restrict__ pi, int nb, int n,
-                     double* __restrict__ d, int* __restrict__ out) {
+                     MK* __restrict__ mk, int* __restrict__ out, double* __restrict__ out_v) {
     VI best{-INFINITY, n};
     for (int b = threadIdx.x; b < nb; b += LS_NT) best = better(best, VI{pv[b], pi[b]});
     best = block_best(best);
     if (threadIdx.x == 0) {
         const int idx = best.i < n ? best.i : -1;
-        if (idx >= 0) d[idx] = 0.0;
+        if (idx >= 0) mk[idx] = MK(0);
         out[0] = idx;
+        if (out_v) out_v[0] = idx >= 0 ? best.v : 0.0;
     }
 }
 
@@ -90,8 +96,25 @@ int loadstep_blocks(int n) {
 void launch_loadstep(const double* x, const double* t, double* d, int n, double* pv, int* pi, int* out,
                      hipStream_t s) {
     const int nb = loadstep_blocks(n);
-    hipLaunchKernelGGL(k_loadstep_partial, dim3(nb), dim3(LS_NT), 0, s, x, t, d, n, pv, pi);
-    hipLaunchKernelGGL(k_loadstep_final, dim3(1), dim3(LS_NT), 0, s, pv, pi, nb, n, d, out);
+    hipLaunchKernelGGL(k_loadstep_partial<double>, dim3(nb), dim3(LS_NT), 0, s, x, t, d, n, pv, pi);
+    hipLaunchKernelGGL(k_loadstep_final<double>, dim3(1), dim3(LS_NT), 0, s, pv, pi, nb, n, d, out,
+                       (double*)nullptr);
+}
+
+void launch_breakstep(const double* x, const double* t, uint8_t* mask, int n, double* pv, int* pi, int* out,
+                      double* out_v, hipStream_t s) {
+    const int nb = loadstep_blocks(n);
+    hipLaunchKernelGGL(k_loadstep_partial<uint8_t>, dim3(nb), dim3(LS_NT), 0, s, x, t, mask, n, pv, pi);
+    hipLaunchKernelGGL(k_loadstep_final<uint8_t>, dim3(1), dim3(LS_NT), 0, s, pv, pi, nb, n, mask, out, out_v);
+}
+
+__global__ void k_fill(double* __restrict__ a, double v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+void launch_fill(double* a, double v, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, a, v, n);
 }
 
 }  // namespace fftcg

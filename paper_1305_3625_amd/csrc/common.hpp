@@ -1,6 +1,7 @@
 // Launchers of the size-independent kernels (common.hip).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace fftcg {
 
@@ -10,5 +11,10 @@ int loadstep_blocks(int n);
 // *out = i* or -1.  pv / pi hold loadstep_blocks(n) partials.
 void launch_loadstep(const double* x, const double* t, double* d, int n, double* pv, int* pi, int* out,
                      hipStream_t s);
+// the same over mask != 0, mask[i*] = 0, and *out_v = x[i*] / t[i*].
+void launch_breakstep(const double* x, const double* t, uint8_t* mask, int n, double* pv, int* pi, int* out,
+                      double* out_v, hipStream_t s);
+// a[i] = v, i < n.
+void launch_fill(double* a, double v, int n, hipStream_t s);
 
 }  // namespace fftcg

@@ -512,7 +512,8 @@ static void fill_info(fftcg_info* info, const SolveState& st, float ms) {
 }
 
 static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, const double* b, const double* x0,
-                           double tol, int maxit, double* x, fftcg_info* info, hipStream_t s) {
+                           double tol, int maxit, double* x, fftcg_info* info, hipStream_t s,
+                           const uint8_t* mask = nullptr) {
     Workspace* w = plan_acquire(plan);
     if (!w) return FFTCG_ENOMEM;
     const EngineOps* ops = plan->ops;
@@ -520,6 +521,7 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
     int rc = FFTCG_OK;
     do {
         fill_slot(w->h_slot, w, x, b, d);
+        w->h_slot->mask = mask;
         init_state(w->h_state, plan, precision, tol, maxit, 50);
         w->h_status[0] = 0;
         w->h_status[1] = 0;
@@ -645,3 +647,64 @@ extern "C" const char* fftcg_strerror(int status) {
 }
 
 extern "C" const char* fftcg_version(void) { return "fftcg 0.1.0 (gfx950)"; }
+
+// ---- quasi-static fracture driver -------------------------------------------
+// Sec. 2: displacement control with uniform fibre stiffness k.  At unit
+// displacement the intact fibres carry f with (I/k + G)_II f_I = 1_I (eq. (2)
+// divided by k, restricted to the intact set I; broken fibres carry no force
+// and are projected out of the solve).  The fibre with the largest f_i/t_i
+// breaks next, at the displacement D = t_i/f_i; then the next step solves
+// again, warm-started from the previous forces.
+extern "C" int fftcg_fracture(fftcg_plan_t plan, int precision, double k, const double* t, int steps, double tol,
+                              int maxit, double* f, int* broken, double* dbreak, int* iters, void* stream) {
+    if (!plan || !t || !f || !broken || !dbreak) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    if (!(k > 0.0) || !isfinite(k) || !(tol > 0.0 && tol < 1.0) || maxit < 1) return FFTCG_EINVAL;
+    const size_t n = (size_t)plan->L * plan->L;
+    if (steps < 1 || (size_t)steps > n || !plan->ops) return FFTCG_EINVAL;
+    const int rc0 = check_device();
+    if (rc0 != FFTCG_OK) return rc0;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* mask = nullptr;
+    double *d = nullptr, *b = nullptr, *pv = nullptr, *outv = nullptr, *h_v = nullptr;
+    int *pi = nullptr, *out = nullptr, *h_i = nullptr;
+    const int nb = loadstep_blocks((int)n);
+    int rc = FFTCG_OK;
+    if (hipMalloc(&mask, n) != hipSuccess || hipMalloc(&d, n * 8) != hipSuccess || hipMalloc(&b, n * 8) != hipSuccess ||
+        hipMalloc(&pv, nb * 8) != hipSuccess || hipMalloc(&pi, nb * 4) != hipSuccess ||
+        hipMalloc(&out, 16) != hipSuccess || hipMalloc(&outv, 16) != hipSuccess ||
+        hipHostMalloc((void**)&h_v, 16, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h_i, 16, hipHostMallocDefault) != hipSuccess)
+        rc = FFTCG_ENOMEM;
+    if (rc == FFTCG_OK) {
+        launch_fill(d, 1.0 / k, (int)n, s);
+        launch_fill(b, 1.0, (int)n, s);
+        if (hipMemsetAsync(mask, 1, n, s) != hipSuccess || hipMemsetAsync(f, 0, n * 8, s) != hipSuccess ||
+            hipGetLastError() != hipSuccess)
+            rc = FFTCG_EDEVICE;
+    }
+    for (int step = 0; step < steps && rc == FFTCG_OK; ++step) {
+        fftcg_info info{};
+        const int st = solve_multipass(plan, precision, d, b, f, tol, maxit, f, &info, s, mask);
+        if (st != FFTCG_OK) {
+            rc = st;
+            break;
+        }
+        launch_breakstep(f, t, mask, (int)n, pv, pi, out, outv, s);
+        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(h_i, out, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(h_v, outv, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        broken[step] = h_i[0];
+        dbreak[step] = h_v[0] > 0.0 ? 1.0 / h_v[0] : INFINITY;
+        if (iters) iters[step] = info.iterations;
+    }
+    (void)hipStreamSynchronize(s);
+    void* dv[] = {mask, d, b, pv, pi, out, outv};
+    for (void* v : dv)
+        if (v) (void)hipFree(v);
+    if (h_v) (void)hipHostFree(h_v);
+    if (h_i) (void)hipHostFree(h_i);
+    return rc;
+}

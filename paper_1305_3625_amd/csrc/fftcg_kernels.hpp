@@ -246,6 +246,16 @@ __device__ __forceinline__ cx<double> ld2f(const float* p) {
     const cx<float> v = gld(reinterpret_cast<const cx<float>*>(p));
     return mkc((double)v.x, (double)v.y);
 }
+// Projection onto the intact entries of a masked solve: (m0, m1) in {0, 1}
+// for the pair at idx (both 1 without a mask).
+struct Mask2 {
+    double m0, m1;
+};
+__device__ __forceinline__ Mask2 mask2(const SlotDesc& sd, size_t idx) {
+    if (!sd.mask) return Mask2{1.0, 1.0};
+    const uint8_t* m = sd.mask + idx;
+    return Mask2{(double)m[0], (double)m[1]};
+}
 
 // ==== prologues of the row-forward pass ====================================
 
@@ -349,6 +359,9 @@ struct ProCheck {
             xv.x += sh.alpha * (double)pv.x;
             xv.y += sh.alpha * (double)pv.y;
         }
+        const Mask2 mk = mask2(sd, idx);  // broken entries carry no force
+        xv.x *= mk.m0;
+        xv.y *= mk.m1;
         st2<double>(sd.x + idx, xv);
         return xv;
     }
@@ -515,6 +528,10 @@ struct EpiCG {
             dv = ld2<double>(sd.d + idx);
         }
         cx<W> qv = mkc(dv.x * pv.x + c0, dv.y * pv.y + c1);
+        if (sd.mask) {
+            const Mask2 mk = mask2(sd, idx);
+            qv = mkc(qv.x * (W)mk.m0, qv.y * (W)mk.m1);
+        }
         st2<W>(q + idx, qv);
         acc[0] += (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
     }
@@ -535,8 +552,10 @@ struct EpiCheck {
         cx<double> xv = ld2<double>(sd.x + idx);
         cx<double> bv = ld2<double>(sd.b + idx);
         cx<double> dv = ld2<double>(sd.d + idx);
-        const double r0 = bv.x - (dv.x * xv.x + c0);
-        const double r1 = bv.y - (dv.y * xv.y + c1);
+        const Mask2 mk = mask2(sd, idx);
+        const double r0 = mk.m0 * (bv.x - (dv.x * xv.x + c0));
+        const double r1 = mk.m1 * (bv.y - (dv.y * xv.y + c1));
+        bv = mkc(mk.m0 * bv.x, mk.m1 * bv.y);
         const W w0 = (W)r0, w1 = (W)r1;
         W* rp = reinterpret_cast<W*>(sd.r) + idx;
         if (sd.st->checks > 0) {  // the first check has no recursive residual yet
@@ -548,7 +567,7 @@ struct EpiCheck {
         acc[1] += xv.x * xv.x + xv.y * xv.y;
         acc[2] += bv.x * bv.x + bv.y * bv.y;
         acc[3] += (double)w0 * (double)w0 + (double)w1 * (double)w1;
-        acc[4] = fmin(acc[4], fmin(dv.x, dv.y));
+        acc[4] = fmin(acc[4], fmin(mk.m0 > 0.0 ? dv.x : 1.0e300, mk.m1 > 0.0 ? dv.y : 1.0e300));
         const bool ok = isfinite(bv.x) && isfinite(bv.y) && isfinite(dv.x) && isfinite(dv.y) &&
                         dv.x >= 0.0 && dv.y >= 0.0;
         acc[5] += ok ? 0.0 : 1.0;
@@ -568,6 +587,11 @@ struct EpiPre {
     static __device__ __forceinline__ void out2(const SlotDesc& sd, int row, int col, W c0, W c1, double* acc) {
         const size_t idx = (size_t)row * L + col;
         const cx<W> rv = ld2<W>(reinterpret_cast<const W*>(sd.r) + idx);
+        if (sd.mask) {
+            const Mask2 mk = mask2(sd, idx);
+            c0 *= (W)mk.m0;
+            c1 *= (W)mk.m1;
+        }
         st2<W>(reinterpret_cast<W*>(sd.z) + idx, mkc(c0, c1));
         acc[0] += (double)rv.x * (double)c0 + (double)rv.y * (double)c1;
     }

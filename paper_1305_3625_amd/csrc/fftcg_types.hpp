@@ -66,6 +66,8 @@ struct SlotDesc {
     double* part;        // reduction partials, NPART_SETS x npart_stride
     SolveState* st;      // CG state
     int* host_status;    // device-visible pinned host word pair, or nullptr
+    const uint8_t* mask; // nullptr, or 1 = intact / 0 = broken per element:
+                         // broken entries are projected out (f_i = 0)
     int active;          // 0: every kernel returns at once for this slot
     int pad_;
 };

@@ -17,5 +17,6 @@ from .configs import (  # noqa: F401
     c4_schedule,
     c4_request,
     c5_sequence,
+    fracture_instance,
     CONFIGS,
 )

@@ -135,3 +135,12 @@ CONFIGS = {
     "C5": dict(L=512, padded=1, eps=1e-3, mode="mixed", tol=1e-8,
                sequences=64, steps=1000),
 }
+
+
+def fracture_instance(s: int, L: int = 64, padded: int = 1, gradient: float = 1.0):
+    """Thresholds for the fracture driver: t = 1e-3 + U(0,1) + gradient * i1/L
+    (a gradient along the row index directs the front); uniform stiffness."""
+    rng = np.random.default_rng([6, s])
+    i1 = np.arange(L, dtype=np.float64)[:, None] / L
+    t = 1e-3 + rng.uniform(0.0, 1.0, (L, L)) + gradient * i1
+    return dict(L=L, padded=padded, t=t, k=1.0)
