@@ -89,6 +89,33 @@ def cpu_baseline(inst, gpu_iters, max_seconds=20.0):
     }
 
 
+def cpu_context():
+    """The oracle's FP64 CG with its numpy-FFT product (one host core) on the
+    other workloads, for context: one periodic L = 64 instance (1e-10), one
+    padded L = 512 instance (1e-10), and 4 requests of the serving mix
+    (one per grid size, 1e-8); residual rule on the recursive residual."""
+    import numpy as np
+    from oracle import apply_fft, cg
+    from workloads import c1_instance, c2_instance, c4_request, spectrum
+    out = {}
+    for name, inst, padded, tol in (("periodic_L64_fp64", c1_instance(0), 0, 1e-10),
+                                    ("padded_L512_fp64", c2_instance(0), 1, 1e-10)):
+        t0 = time.perf_counter()
+        _, info = cg(lambda v: apply_fft(inst["ghat"], inst["d"], v, padded), inst["b"], tol=tol)  # noqa: B023
+        el = time.perf_counter() - t0
+        out[name] = dict(solves_per_s=round(1.0 / el, 3), iterations=info["iterations"])
+    t0 = time.perf_counter()
+    its = []
+    for j, M in enumerate((128, 256, 512, 1024)):
+        r = c4_request(10000 + j, M)
+        gh = spectrum(M, 1e-3)
+        _, info = cg(lambda v: apply_fft(gh, r["d"], v, 1), r["b"], tol=1e-8)  # noqa: B023
+        its.append(info["iterations"])
+    el = time.perf_counter() - t0
+    out["serving_sample_4_requests"] = dict(solves_per_s=round(4 / el, 2), iterations_mean=float(np.mean(its)))
+    return out
+
+
 def oracle_certify(insts, xs):
     """Largest certified error bound of the GPU solutions xs, from the
     oracle's FP64 residual b - A x (numpy-FFT product) and its lambda_lb."""
@@ -298,6 +325,62 @@ def solve_set_bench(insts, precision, tol):
     return out
 
 
+def fracture_bench(L=512, steps=200, precond=True):
+    """The quasi-static fracture driver (Sec. 2): zero-padded L x L grid,
+    eps = 1e-3, uniform stiffness, thresholds with a gradient; `steps` fibres
+    broken one per warm-started mixed-precision solve."""
+    import numpy as np
+    import torch
+    from paper_1305_3625_amd import binding
+    from workloads import fracture_instance, spectrum
+    inst = fracture_instance(0, L=L)
+    plan = binding.Plan(L, 1, spectrum(2 * L, 1e-3))
+    if precond:
+        plan.set_precond(binding.PRECOND_CIRCULANT)
+    t = torch.from_numpy(inst["t"]).to("cuda")
+    f = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    plan.fracture(inst["k"], t, f, 2, tol=1e-8)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, broken, dbreak, iters = plan.fracture(inst["k"], t, f, steps, tol=1e-8)
+    el = time.perf_counter() - t0
+    if st != binding.OK:
+        raise SystemExit(f"fracture driver failed: {binding.STATUS_NAMES.get(st, st)}")
+    plan.close()
+    return dict(L=L, steps=steps, preconditioned=precond, seconds=round(el, 3),
+                steps_per_s=round(steps / el, 1), iterations_per_step_mean=round(float(np.mean(iters)), 2),
+                first_dbreak=float(dbreak[0]), last_dbreak=float(dbreak[-1]))
+
+
+def large_bench(L=4096, steps=2):
+    """Mixed solves on the largest grid (zero-padded L = 4096, M = 8192),
+    eps = 1e-4, d with 30% zeros, b ~ N(0,1); plain and preconditioned."""
+    import numpy as np
+    import torch
+    from paper_1305_3625_amd import binding
+    from workloads import padded_instance
+    inst = padded_instance(L, [97, 0], eps=1e-4, normal_b=True)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    D = torch.from_numpy(inst["d"]).to("cuda")
+    B = torch.from_numpy(inst["b"]).to("cuda")
+    X = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    out = {}
+    for label, pre in (("plain", binding.PRECOND_NONE), ("preconditioned", binding.PRECOND_CIRCULANT)):
+        plan.set_precond(pre)
+        plan.solve(D, B, X, tol=1e-8, precision=binding.MIXED)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [plan.solve(D, B, X, tol=1e-8, precision=binding.MIXED) for _ in range(steps)]
+        el = time.perf_counter() - t0
+        out[label] = dict(solves_per_s=round(steps / el, 3), ms_per_solve=round(el / steps * 1e3, 2),
+                          iterations_mean=round(float(np.mean([i["iterations"] for i in infos])), 1),
+                          error_bound_max=max(i["error_bound"] for i in infos))
+    plan.close()
+    del D, B, X
+    torch.cuda.empty_cache()
+    return dict(L=L, M=2 * L, **out)
+
+
 def loadstep_bench(n_seq=64, steps=1000):
     """Load-stepped sequences (warm-started solves, device argmax break rule),
     all submitted to the server at once."""
@@ -437,6 +520,7 @@ def main(argv=None):
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(insts[0], infos[0]["iterations"])
+        cpu["other_workloads"] = cpu_context()
         if not a.no_oracle_check:
             xs = [X[j].cpu().numpy() for j in range(min(len(insts), a.steps))]
             cpu["oracle_error_bound_max"] = oracle_certify(insts, xs)
@@ -477,6 +561,8 @@ def main(argv=None):
             "padded_L512_fp64_10_instances": solve_set_bench([c2_instance(s) for s in range(10)],
                                                              binding.FP64, 1e-10),
             "loadstep_L512_mixed": loadstep_bench(a.seq, a.seq_steps) if a.seq > 0 else None,
+            "fracture_L512_mixed_preconditioned": fracture_bench(512, 200, True),
+            "padded_L4096_mixed": large_bench(),
         }
 
     out = {

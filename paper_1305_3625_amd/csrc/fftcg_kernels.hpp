@@ -46,11 +46,16 @@ struct Geo {
     static constexpr int ER = fft_elems(N);
     static constexpr int PR = N / ER;
     static constexpr int ROW_WORDS = LdsLay<T, 1, 4, 1>::words(N);
-    static constexpr int ROW_LDS_CAP = 73728 / (int)sizeof(cx<T>);  // two workgroups per CU
+    // LDS budget per workgroup: 72 KB (two workgroups per CU); on the largest
+    // grid (M = 8192) one workgroup of twice the size takes 144 KB, so that
+    // rows and column tiles still come in pairs and W moves in 32-byte runs
+    static constexpr int LDS_CAP_BYTES = M >= 8192 ? 147456 : 73728;
+    static constexpr int ROW_LDS_CAP = LDS_CAP_BYTES / (int)sizeof(cx<T>);
 #ifndef FFTCG_ROW_NT
 #define FFTCG_ROW_NT 256
 #endif
-    static constexpr int RPW0 = cmin(L, cmax(1, FFTCG_ROW_NT / PR));
+    static constexpr int ROW_NT = M >= 8192 ? 2 * FFTCG_ROW_NT : FFTCG_ROW_NT;
+    static constexpr int RPW0 = cmin(L, cmax(1, ROW_NT / PR));
     static constexpr int RPW_fit(int r) { return (r > 1 && r * ROW_WORDS > ROW_LDS_CAP) ? RPW_fit(r / 2) : r; }
     static constexpr int RPW = RPW_fit(RPW0);
     static constexpr int ROW_THREADS = RPW * PR;
@@ -58,7 +63,7 @@ struct Geo {
     // column pass
     static constexpr int EC = fft_elems(M);
     static constexpr int PC = M / EC;
-    static constexpr int COL_LDS_CAP = 73728 / (int)sizeof(cx<T>);
+    static constexpr int COL_LDS_CAP = LDS_CAP_BYTES / (int)sizeof(cx<T>);
     static constexpr int TT_fit(int t) {
         return (t > 1 && (t * M + (t * M) / 16 + t > COL_LDS_CAP || t * PC > 1024)) ? TT_fit(t / 2) : t;
     }
