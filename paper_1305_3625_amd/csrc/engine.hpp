@@ -41,6 +41,10 @@ struct EngineOps {
                      hipStream_t s);
     void (*check_pcg)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
                       hipStream_t s);
+    // the initial check of a solve started from x = 0 (no product: r = b)
+    void (*check0)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride, hipStream_t s);
+    void (*check0_pcg)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
+                       hipStream_t s);
 };
 
 const EngineOps* find_engine(int M, int pad);

@@ -191,6 +191,42 @@ void check_pcg_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslot
         check_pcg_t<float>(pt, slots, nslots, stride, s);
 }
 
+// The initial check of a solve started from zero (x = 0, e = 0 already
+// written by the host): r = b in one pass, then the finaliser (and, for the
+// preconditioned solve, z = P^{-1} r).
+template <typename W>
+void check0_t(bool pcg, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    constexpr int RTW = G<W>::ROW_THREADS, CTW = G<W>::COL_THREADS, RBW = G<W>::ROW_BLOCKS;
+    const ByPtr sp{slots};
+    hipLaunchKernelGGL((k_check_zero<W, 256>), dim3(G<double>::ROW_BLOCKS, nslots), dim3(256), 0, s, sp, LL * LL,
+                       stride);
+    hipLaunchKernelGGL((k_check_final<256>), dim3(1, nslots), dim3(256), 0, s, sp, G<double>::ROW_BLOCKS,
+                       pcg ? RBW : g4_blocks(), stride, LL * LL);
+    if (pcg) {
+        const Tab<W> tabw = tab_of<W>(pt);
+        hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProPre<W>, ByPtr, RTW>), dim3(RBW, nslots), dim3(RTW), 0, s, tabw,
+                           sp, 0, stride);
+        hipLaunchKernelGGL((k_col<W, M, PAD, GatePre, ByPtr, CTW, true>), dim3(G<W>::NTILE, nslots), dim3(CTW), 0,
+                           s, tabw, sp);
+        hipLaunchKernelGGL((k_row_inv<W, M, PAD, EpiPre<W, GatePre>, ByPtr, RTW>), dim3(RBW, nslots), dim3(RTW), 0,
+                           s, tabw, sp, stride);
+    }
+}
+
+void check0_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    if (prec == 0)
+        check0_t<double>(false, pt, slots, nslots, stride, s);
+    else
+        check0_t<float>(false, pt, slots, nslots, stride, s);
+}
+
+void check0_pcg_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
+    if (prec == 0)
+        check0_t<double>(true, pt, slots, nslots, stride, s);
+    else
+        check0_t<float>(true, pt, slots, nslots, stride, s);
+}
+
 const EngineOps kOps = {M,
                         PAD,
                         LL,
@@ -204,7 +240,9 @@ const EngineOps kOps = {M,
                         &iter_fn,
                         &check_fn,
                         &iter_pcg_fn,
-                        &check_pcg_fn};
+                        &check_pcg_fn,
+                        &check0_fn,
+                        &check0_pcg_fn};
 
 }  // namespace
 

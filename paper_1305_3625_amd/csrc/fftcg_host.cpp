@@ -465,7 +465,12 @@ void fftcg::init_state(SolveState* h, const fftcg_plan_s* p, int precision, doub
     h->best_rt = INFINITY;
     // mixed mode: residual replacement each time the FP32 recursive residual
     // has fallen by 1e-2 since the last one (reliable updates)
-    h->delta2 = precision == FFTCG_MIXED ? 1e-4 : 0.0;
+    // (preconditioned solves: by 1e-4, as they run only tens of iterations,
+    // so the FP32 recursion drifts little between replacements)
+#ifndef FFTCG_CG_DELTA2
+#define FFTCG_CG_DELTA2 1e-4
+#endif
+    h->delta2 = precision == FFTCG_MIXED ? (p->precond == FFTCG_PRECOND_CIRCULANT ? 1e-8 : FFTCG_CG_DELTA2) : 0.0;
     h->rho_ref = 0.0;
     h->pcg = p->precond == FFTCG_PRECOND_CIRCULANT ? 1 : 0;
 }
@@ -550,8 +555,12 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
         const bool pcg = plan->precond == FFTCG_PRECOND_CIRCULANT;
         const auto iter = pcg ? ops->iter_pcg : ops->iter;
         const auto check = pcg ? ops->check_pcg : ops->check;
-        check(precision, plan->tabs, w->slot, 1, plan->stride, s);
-        const int K = chunk_iters_for(plan->L);
+        // from zero the first residual is b itself: no product
+        const auto first = x0 ? check : (pcg ? ops->check0_pcg : ops->check0);
+        first(precision, plan->tabs, w->slot, 1, plan->stride, s);
+        // preconditioned solves check every few iterations (they converge in
+        // tens): shorter chunks leave fewer iterations idle behind a check
+        const int K = pcg ? std::max(2, chunk_iters_for(plan->L) / 2) : chunk_iters_for(plan->L);
         const long max_chunks = (long)maxit + 64;
         long c = 0;
         bool finished = false;

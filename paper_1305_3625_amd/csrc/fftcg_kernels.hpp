@@ -922,6 +922,44 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
     if (threadIdx.x == 0) sd.part[PS_RR * stride + blockIdx.x] = s;
 }
 
+// The first FP64 check of a solve started from x = 0: r = b - A 0 = b, so
+// no product is needed.  One pass over b and d writes r and the check's
+// partials (the same values the full check would produce, bitwise: C 0 and
+// d 0 are exactly zero); the finaliser then decides as usual.  npart blocks.
+template <typename W, int NT>
+__global__ void __launch_bounds__(NT) k_check_zero(ByPtr slot, int n, int stride) {
+    __shared__ double red[(NT + 63) / 64];
+    const SlotDesc& sd = slot.get();
+    if (!GateCheck::ok(sd)) return;
+    const int npairs = n / 2;
+    const int per = (npairs + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * per;
+    const int hi = lo + per < npairs ? lo + per : npairs;
+    double acc[8] = {0, 0, 0, 0, 1.0e300, 0, 0, 0};
+    for (int q = lo + threadIdx.x; q < hi; q += NT) {
+        const size_t idx = 2 * (size_t)q;
+        const cx<double> b2 = ld2<double>(sd.b + idx), d2 = ld2<double>(sd.d + idx);
+        const Mask2 mk = mask2(sd, idx);
+        const double r0 = mk.m0 * b2.x, r1 = mk.m1 * b2.y;
+        const W w0 = (W)r0, w1 = (W)r1;
+        st2<W>(reinterpret_cast<W*>(sd.r) + idx, mkc(w0, w1));
+        acc[0] += r0 * r0 + r1 * r1;
+        acc[2] += r0 * r0 + r1 * r1;
+        acc[3] += (double)w0 * (double)w0 + (double)w1 * (double)w1;
+        acc[4] = fmin(acc[4], fmin(mk.m0 > 0.0 ? d2.x : 1.0e300, mk.m1 > 0.0 ? d2.y : 1.0e300));
+        const bool ok = isfinite(r0) && isfinite(r1) && isfinite(d2.x) && isfinite(d2.y) && d2.x >= 0.0 &&
+                        d2.y >= 0.0;
+        acc[5] += ok ? 0.0 : 1.0;
+        acc[7] += d2.x + d2.y;
+    }
+    const int sets[8] = {PS_CHK_R, PS_CHK_X, PS_CHK_B, PS_CHK_RW, PS_CHK_DMIN, PS_CHK_BAD, PS_CHK_DIFF, PS_CHK_DSUM};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const double v = (a == 4) ? block_min<NT>(acc[a], red) : block_sum<NT>(acc[a], red);
+        if (threadIdx.x == 0) sd.part[sets[a] * stride + blockIdx.x] = v;
+    }
+}
+
 // Single-block finaliser of an FP64 check: stop decision, residual
 // replacement, restart guard, and status for the host.
 template <int NT>
