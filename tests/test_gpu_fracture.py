@@ -59,3 +59,22 @@ def test_fracture_errors():
         args.update(bad)
         st, *_ = plan.fracture(args["k"], t, f, args["steps"], tol=args["tol"], maxit=args["maxit"])
         assert st == binding.EINVAL, bad
+
+
+def test_fracture_breaks_everything():
+    """L = 4: all 16 fibres break, each exactly once, in an order the oracle
+    accepts; the last step has a single intact fibre."""
+    import torch
+    L = 4
+    inst = fracture_instance(3, L=L)
+    gh = spectrum(2 * L, 1e-2)
+    plan = binding.Plan(L, 1, gh)
+    f = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    banner("fracture-all")
+    st, broken, dbreak, iters = plan.fracture(inst["k"], dev(inst["t"]), f, L * L, tol=1e-10,
+                                              precision=binding.FP64)
+    assert st == binding.OK
+    assert sorted(broken.tolist()) == list(range(L * L))
+    _, fo_dbreak, _, _ = fracture_sequence(gh, inst["k"], inst["t"], L * L, 1, replay=broken)
+    np.testing.assert_allclose(dbreak, fo_dbreak, rtol=1e-8)
+    assert float(torch.abs(f).sum()) > 0.0  # the last intact fibre carried the load

@@ -157,3 +157,57 @@ def test_set_precond_errors():
         plan.set_precond(7)
     plan.set_precond(binding.PRECOND_CIRCULANT)
     plan.set_precond(binding.PRECOND_NONE)
+
+
+def test_set_precond_refused_while_served():
+    M = 1024
+    plan = binding.Plan(M // 2, 1, spectrum(M, 1e-3))
+    r = c4_request(600, M)
+    srv = binding.Server(memory_budget=1 << 30)
+    banner("pcg-in-use")
+    st, tk = srv.submit(plan, r["d"], r["b"], tol=1e-8)
+    assert st == binding.OK
+    with pytest.raises(binding.FftcgError):
+        plan.set_precond(binding.PRECOND_CIRCULANT)  # the request holds the plan
+    res = _wait(srv, [tk], M // 2)[tk]
+    assert res.status == binding.OK
+    plan.set_precond(binding.PRECOND_CIRCULANT)
+    srv.close()
+
+
+def test_pcg_warm_start_and_zero_rhs():
+    import torch
+    L = 128
+    inst, xr, _ = _reference(128, 1)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    plan.set_precond(binding.PRECOND_CIRCULANT)
+    banner("pcg-warm")
+    x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    cold = plan.solve(dev(inst["d"]), dev(inst["b"]), x, tol=1e-10, precision=binding.FP64)
+    x0 = dev(xr * (1.0 + 1e-3))  # near the solution: 3 fewer orders of magnitude to go
+    info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, x0=x0, tol=1e-10, precision=binding.FP64)
+    assert info["status"] == binding.OK and info["iterations"] < cold["iterations"]
+    assert relerr(host(x), xr) <= 1e-10
+    z = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(inst["d"]), z, x, tol=1e-10, precision=binding.MIXED)
+    assert info["status"] == binding.OK and info["iterations"] == 0
+    assert float(torch.abs(x).max()) == 0.0
+
+
+def test_pcg_server_small_class():
+    """L = 32 (a fused-engine class without a preconditioner) runs on the
+    multi-pass engine once the plan is preconditioned."""
+    M = 64
+    gh = spectrum(M, 1e-3)
+    plan = binding.Plan(M // 2, 1, gh)
+    plan.set_precond(binding.PRECOND_CIRCULANT)
+    reqs = [c4_request(700 + k, M) for k in range(3)]
+    srv = binding.Server(memory_budget=1 << 28)
+    banner("pcg-serve-small")
+    tks = [srv.submit(plan, r["d"], r["b"], tol=1e-8)[1] for r in reqs]
+    res = _wait(srv, tks, M // 2)
+    for r, tk in zip(reqs, tks):
+        assert res[tk].status == binding.OK
+        xr, _ = reference_solve(gh, r["d"], r["b"], 1)
+        assert relerr(res[tk].x, xr) <= 1e-8
+    srv.close()
