@@ -24,6 +24,7 @@
 // k = kt * TT + kk, so a column tile is one contiguous block and each row
 // writes runs of RPW * TT complex values.
 #pragma once
+#include <stddef.h>
 #include <type_traits>
 #include "fftcg_dev.hpp"
 #include "fftcg_types.hpp"
@@ -204,23 +205,36 @@ struct ByVal {
     __device__ __forceinline__ const SlotDesc& get() const { return s; }
 };
 
-// gates: which slots a kernel works on
+// gates: which slots a kernel works on (inactive slots first, then the
+// solve's state; pause and done are adjacent words, read with one load).
+__device__ __forceinline__ typename VecT<int, 2>::type pause_done(const SolveState* st) {
+    static_assert(offsetof(SolveState, done) == offsetof(SolveState, pause) + sizeof(int) &&
+                      offsetof(SolveState, pause) % 8 == 0,
+                  "pause and done form one aligned 8-byte word");
+    return *gbl(reinterpret_cast<const typename VecT<int, 2>::type*>(&st->pause));
+}
 struct GateAlways {
     static __device__ __forceinline__ bool ok(const SlotDesc&) { return true; }
 };
 struct GateIter {  // CG iteration kernels
     static __device__ __forceinline__ bool ok(const SlotDesc& sd) {
-        return sd.active && !sd.st->done && !sd.st->pause;
+        if (!sd.active) return false;
+        const auto pd = pause_done(sd.st);
+        return (pd.x | pd.y) == 0;
     }
 };
 struct GateCheck {  // FP64 check kernels
     static __device__ __forceinline__ bool ok(const SlotDesc& sd) {
-        return sd.active && !sd.st->done && sd.st->pause;
+        if (!sd.active) return false;
+        const auto pd = pause_done(sd.st);
+        return pd.x != 0 && pd.y == 0;
     }
 };
 struct GatePre {  // preconditioner after a check that continues the solve
     static __device__ __forceinline__ bool ok(const SlotDesc& sd) {
-        return sd.active && !sd.st->done && sd.st->need_pre;
+        if (!sd.active) return false;
+        const int done = *gbl(&sd.st->done), need = *gbl(&sd.st->need_pre);
+        return (done == 0) & (need != 0);
     }
 };
 
@@ -747,11 +761,7 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
 #pragma unroll
         for (int u = 0; u < E / RL; ++u)
 #pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                const int m = (j + u * P) + r * (M / RL);
-                const int mp = m <= M - m ? m : M - m;
-                v[u * RL + r] = scalec(v[u * RL + r], gpre[u * RL + r]);
-            }
+            for (int r = 0; r < RL; ++r) v[u * RL + r] = scalec(v[u * RL + r], gpre[u * RL + r]);
     }
     fft_run<T, M, M, +1, true, false>(v, lay, j, tab.tw);
     constexpr int RZ = fft_radix(M, true, NSTG - 1);
