@@ -7,9 +7,6 @@
 
 namespace fftcg {
 
-template <typename T>
-struct cx;
-
 struct PlanTabs {
     const void* tw32;   // cx<float>[M]
     const void* ghq32;  // float, tile layout of the FP32 column pass

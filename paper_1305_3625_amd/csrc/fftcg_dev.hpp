@@ -17,7 +17,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Largest radix of a stage (16, 8 or 4).  It is a per-translation-unit
+// choice (the fused engine takes 4 or 8 on the smallest grids), so every
+// definition that depends on it lives in an inline namespace named after it
+// and units built with different radices never share a symbol.
+#ifndef FFTCG_MAXR
+#define FFTCG_MAXR 16
+#endif
+#define FFTCG_RNS_CAT2(a, b) a##b
+#define FFTCG_RNS_CAT(a, b) FFTCG_RNS_CAT2(a, b)
+#define FFTCG_RADIX_NS FFTCG_RNS_CAT(radix, FFTCG_MAXR)
+
 namespace fftcg {
+inline namespace FFTCG_RADIX_NS {
 
 template <typename T>
 struct cx {
@@ -152,9 +164,6 @@ __device__ __forceinline__ void dft(cx<T>* v) {
 // ---- radix plans ----------------------------------------------------------
 // Forward order: MAXR, MAXR, ..., then the remainder radix.  Reversed order:
 // remainder first.  Lengths below MAXR use one stage.  MAXR = 16 by default.
-#ifndef FFTCG_MAXR
-#define FFTCG_MAXR 16
-#endif
 constexpr int MAXR = FFTCG_MAXR;
 constexpr int LGMAXR = MAXR == 16 ? 4 : (MAXR == 8 ? 3 : 2);
 __host__ __device__ constexpr int fft_elems(int N) { return N >= MAXR ? MAXR : N; }
@@ -374,4 +383,5 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
     return block_sum<NT>(s, sh);
 }
 
+}  // namespace FFTCG_RADIX_NS
 }  // namespace fftcg

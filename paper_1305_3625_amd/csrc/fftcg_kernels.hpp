@@ -30,6 +30,7 @@
 #include "fftcg_types.hpp"
 
 namespace fftcg {
+inline namespace FFTCG_RADIX_NS {
 
 #ifndef FFTCG_STATUS_CODES
 #define FFTCG_STATUS_CODES
@@ -1010,4 +1011,5 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
 }
 
 
+}  // namespace FFTCG_RADIX_NS
 }  // namespace fftcg

@@ -26,6 +26,7 @@
 #include "fused.hpp"
 
 namespace fftcg {
+inline namespace FFTCG_RADIX_NS {
 
 constexpr int FNT = 256;  // threads of a fused workgroup
 
@@ -487,4 +488,5 @@ __global__ void __launch_bounds__(FNT) k_fused_apply(FusedTabs ft, const double*
         });
 }
 
+}  // namespace FFTCG_RADIX_NS
 }  // namespace fftcg
