@@ -31,7 +31,7 @@ METRIC = "FFT-CG solves/s + HBM GB/s at L=2048; served p50/p99 latency vs plain 
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_col_M4096_fp32_traffic.json")
 KERNEL_SOURCES = ["paper_1305_3625_amd/csrc/fftcg_kernels.hpp", "paper_1305_3625_amd/csrc/fftcg_dev.hpp",
-                  "paper_1305_3625_amd/csrc/engine_inst.hip"]
+                  "paper_1305_3625_amd/csrc/engine_inst.hip", "paper_1305_3625_amd/build.py"]
 
 
 def kernel_hash():

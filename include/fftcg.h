@@ -64,8 +64,8 @@ extern "C" {
 #define FFTCG_MIXED 1
 
 /* ---- engines (fftcg_plan_set_engine) -----------------------------------
- * AUTO     : the fused engine for L <= 64 (single solves and server
- *            classes alike), the multi-pass engine above.
+ * AUTO     : the fused engine for M <= 64 in single solves and for
+ *            M <= 128 in server classes, the multi-pass engine above.
  * MULTIPASS: three HBM passes per product (row R2C, column FFT*ghat*IFFT,
  *            row C2R + epilogue); every grid.
  * FUSED    : one workgroup per solve, whole CG loop in one kernel, the

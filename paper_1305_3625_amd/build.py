@@ -35,8 +35,24 @@ CXXFLAGS = [
     f"-I{INC}", f"-I{CSRC}",
 ]
 
-ENGINE_SIZES = [(m, 0) for m in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)] + \
-               [(m, 1) for m in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)]
+
+def engine_radix(m: int) -> int:
+    """Largest radix of the multi-pass engine on an M x M grid.  Below
+    M = 4096 a pass of one solve has too little work to fill the GPU with
+    radix-16 threads; smaller radices spread it over four or two times as
+    many threads at the cost of more LDS exchanges.  Radix 4 up to M = 256,
+    radix 8 up to M = 2048 (it keeps most of radix 4's gain on single solves
+    and is the better one with many solves batched), radix 16 from M = 4096
+    on.  Solves/s of padded mixed solves batched 1 / 4 / 16 / 64 at a time
+    (radix 4; 8; 16): L = 256: 482/1250/1037/2048; 423/1140/1894/2517;
+    330/805/1051/1958.  L = 512: 336/570/849/807; 318/557/652/860;
+    251/468/588/797.  L = 2048, one solve, per product (eps 1e-3): radix 16
+    95.5 us, radix 8 117.9 us."""
+    return 4 if m <= 256 else (8 if m <= 2048 else 16)
+
+
+ENGINE_SIZES = [(m, 0, engine_radix(m)) for m in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)] + \
+               [(m, 1, engine_radix(m)) for m in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)]
 
 # (M, padded, largest radix) of the fused engine: on the smallest grids
 # radix-4 or radix-8 stages spread a transform over more threads, which
@@ -64,8 +80,8 @@ def _jobs(build_dir, extra):
         src = os.path.join(CSRC, s)
         lang = ["-x", "hip"] if s.endswith(".cpp") else []
         yield [HIPCC, *CXXFLAGS, *extra, *lang, "-c", src, "-o", obj(os.path.splitext(s)[0])]
-    for m, pad in ENGINE_SIZES:
-        yield [HIPCC, *CXXFLAGS, *extra, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", "-c",
+    for m, pad, maxr in ENGINE_SIZES:
+        yield [HIPCC, *CXXFLAGS, *extra, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", f"-DFFTCG_MAXR={maxr}", "-c",
                os.path.join(CSRC, "engine_inst.hip"), "-o", obj(f"engine_{m}_{pad}")]
     for m, pad, maxr in FUSED_SIZES:
         yield [HIPCC, *CXXFLAGS, *extra, f"-DFFTCG_M={m}", f"-DFFTCG_PAD={pad}", f"-DFFTCG_MAXR={maxr}", "-c",

@@ -313,14 +313,23 @@ extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) {
 // on MI355X: 19-31 us against 30-45 us per product up to L = 64); from
 // L = 128 on, the fused engine's serial rounds cost more than the launches
 // and the multi-pass engine takes over, for single solves and server classes.
+// AUTO: a single solve takes the fused engine up to M = 64; a server class,
+// whose slots share each launch of the multi-pass engine, up to M = 128
+// (measured crossovers: at M = 128 one fused solve is 15-25% slower than a
+// multi-pass one, while 64 batched solves run as fast or faster fused).
 int fftcg::plan_engine(const fftcg_plan_s* p) {
     if (p->precond != FFTCG_PRECOND_NONE) return FFTCG_ENGINE_MULTIPASS;  // the fused engine has no preconditioner
     if (p->engine == FFTCG_ENGINE_AUTO)
-        return p->fused_ok && p->L <= 64 ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
+        return p->fused_ok && p->M <= 64 ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
     return p->engine;
 }
 
-int fftcg::server_engine(const fftcg_plan_s* p) { return plan_engine(p); }
+int fftcg::server_engine(const fftcg_plan_s* p) {
+    if (p->precond != FFTCG_PRECOND_NONE) return FFTCG_ENGINE_MULTIPASS;
+    if (p->engine == FFTCG_ENGINE_AUTO)
+        return p->fused_ok && p->M <= 128 ? FFTCG_ENGINE_FUSED : FFTCG_ENGINE_MULTIPASS;
+    return p->engine;
+}
 
 extern "C" int fftcg_plan_set_engine(fftcg_plan_t plan, int engine) {
     if (!plan) return FFTCG_EINVAL;
