@@ -45,7 +45,7 @@ def test_apply_small_direct(L, padded, engine):
         assert err <= tol, (prec, err)
 
 
-@pytest.mark.parametrize("L,padded", [(256, 0), (256, 1), (512, 1), (1024, 0), (1024, 1), (2048, 0), (2048, 1)])
+@pytest.mark.parametrize("L,padded", [(256, 0), (256, 1), (512, 0), (512, 1), (1024, 0), (1024, 1), (2048, 0), (2048, 1)])
 def test_apply_large_fft_route(L, padded):
     M = 2 * L if padded else L
     gh = spectrum(M, 1e-4)

@@ -98,10 +98,12 @@ def _serving_reference(L, padded):
     return _REFS[(L, padded)]
 
 
-@pytest.mark.parametrize("L,padded", [(32, 1), (64, 1), (128, 1), (128, 0), (256, 0)])
+@pytest.mark.parametrize("L,padded", [(32, 1), (64, 1), (128, 1), (128, 0), (256, 0), (256, 1)])
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS, binding.ENGINE_FUSED])
 def test_serving_grids(L, padded, mode, engine):
+    if engine == binding.ENGINE_FUSED and (2 * L if padded else L) > 256:
+        pytest.skip("the fused engine serves M <= 256")
     prec, tol, bar = mode
     inst, xr = _serving_reference(L, padded)
     plan = binding.Plan(L, padded, inst["ghat"])
