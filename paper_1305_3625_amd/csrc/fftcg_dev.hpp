@@ -374,6 +374,39 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
     return s;
 }
 
+// N block reductions in one exchange: every wave reduces its N values with
+// the shuffle tree, the wave results go to sh[a * NW + wave], and thread
+// a < N combines set a over the waves in index order (a sum, or a min where
+// bit a of MINMASK is set).  The order is that of block_sum / block_min, so
+// the results are bitwise the same; two barriers instead of 2 N.  The
+// result is valid in threads 0..N-1 (thread a holds set a).  sh must hold
+// N * NW doubles, NW = NT / 64 (NT a multiple of 64).
+template <int NT, int N, unsigned MINMASK>
+__device__ __forceinline__ double block_reduce_n(const double* acc, double* sh) {
+    static_assert(NT % 64 == 0, "whole waves");
+    constexpr int NW = NT / 64;
+    double w[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) w[a] = ((MINMASK >> a) & 1u) ? wave_min(acc[a]) : wave_sum(acc[a]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) sh[a * NW + (threadIdx.x >> 6)] = w[a];
+    }
+    __syncthreads();
+    const int a = threadIdx.x;
+    double r = 0.0;
+    if (a < N) {
+        if ((MINMASK >> a) & 1u) {
+            r = sh[a * NW];
+            for (int v = 1; v < NW; ++v) r = fmin(r, sh[a * NW + v]);
+        } else {
+            for (int v = 0; v < NW; ++v) r += sh[a * NW + v];
+        }
+    }
+    return r;
+}
+
 // Sum of n partials in a fixed order (thread t takes t, t+NT, ...).
 template <int NT>
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, double* sh) {

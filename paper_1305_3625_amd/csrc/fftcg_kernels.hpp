@@ -783,7 +783,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
     constexpr int WORDS = G::ROW_WORDS;
     static_assert(NT == G::ROW_THREADS, "row-inverse block size");
     __shared__ cx<T> lds[RPW * WORDS];
-    __shared__ double red[(NT + 63) / 64];
+    __shared__ double red[(Epi::NACC > 1 ? Epi::NACC : 1) * ((NT + 63) / 64)];
     const SlotDesc& sd = slot.get();
     if (!Epi::begin(sd)) return;
     const int tid = threadIdx.x;
@@ -853,10 +853,16 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
         } else {
             const int sets[8] = {PS_CHK_R,    PS_CHK_X,   PS_CHK_B,    PS_CHK_RW,
                                  PS_CHK_DMIN, PS_CHK_BAD, PS_CHK_DIFF, PS_CHK_DSUM};
+            if constexpr (NT % 64 == 0) {
+                // set 4 (min d) is a minimum, the others sums
+                const double s = block_reduce_n<NT, 8, 1u << 4>(acc, red);
+                if (tid < 8) part[sets[tid] * stride + blockIdx.x] = s;
+            } else {
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const double s = (a == 4) ? block_min<NT>(acc[a], red) : block_sum<NT>(acc[a], red);
-                if (tid == 0) part[sets[a] * stride + blockIdx.x] = s;
+                for (int a = 0; a < 8; ++a) {
+                    const double s = (a == 4) ? block_min<NT>(acc[a], red) : block_sum<NT>(acc[a], red);
+                    if (tid == 0) part[sets[a] * stride + blockIdx.x] = s;
+                }
             }
         }
     }
@@ -939,7 +945,7 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
 // d 0 are exactly zero); the finaliser then decides as usual.  npart blocks.
 template <typename W, int NT>
 __global__ void __launch_bounds__(NT) k_check_zero(ByPtr slot, int n, int stride) {
-    __shared__ double red[(NT + 63) / 64];
+    __shared__ double red[8 * ((NT + 63) / 64)];
     const SlotDesc& sd = slot.get();
     if (!GateCheck::ok(sd)) return;
     const int npairs = n / 2;
@@ -964,18 +970,16 @@ __global__ void __launch_bounds__(NT) k_check_zero(ByPtr slot, int n, int stride
         acc[7] += d2.x + d2.y;
     }
     const int sets[8] = {PS_CHK_R, PS_CHK_X, PS_CHK_B, PS_CHK_RW, PS_CHK_DMIN, PS_CHK_BAD, PS_CHK_DIFF, PS_CHK_DSUM};
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        const double v = (a == 4) ? block_min<NT>(acc[a], red) : block_sum<NT>(acc[a], red);
-        if (threadIdx.x == 0) sd.part[sets[a] * stride + blockIdx.x] = v;
-    }
+    const double v = block_reduce_n<NT, 8, 1u << 4>(acc, red);  // set 4 (min d) a minimum
+    if (threadIdx.x < 8) sd.part[sets[threadIdx.x] * stride + blockIdx.x] = v;
 }
 
 // Single-block finaliser of an FP64 check: stop decision, residual
 // replacement, restart guard, and status for the host.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, int npart_rr, int stride, int n) {
-    __shared__ double red[(NT + 63) / 64];
+    __shared__ double red[8 * ((NT + 63) / 64)];
+    __shared__ double s_tot[8];
     __shared__ int s_update;
     const SlotDesc& sd = slot.get();
     if (!sd.active) return;
@@ -984,17 +988,24 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
         if (threadIdx.x == 0) publish_status(sd, st->done, st->status, st->gen, st->iters);
         return;
     }
-    const double* part = sd.part;
-    const double R = sum_partials<NT>(part + PS_CHK_R * stride, npart_chk, red);
-    const double X = sum_partials<NT>(part + PS_CHK_X * stride, npart_chk, red);
-    const double B = sum_partials<NT>(part + PS_CHK_B * stride, npart_chk, red);
-    const double RW = sum_partials<NT>(part + PS_CHK_RW * stride, npart_chk, red);
-    const double BAD = sum_partials<NT>(part + PS_CHK_BAD * stride, npart_chk, red);
-    const double DIFF = sum_partials<NT>(part + PS_CHK_DIFF * stride, npart_chk, red);
-    const double DSUM = sum_partials<NT>(part + PS_CHK_DSUM * stride, npart_chk, red);
-    double dmin = 1.0e300;
-    for (int i = threadIdx.x; i < npart_chk; i += NT) dmin = fmin(dmin, part[PS_CHK_DMIN * stride + i]);
-    dmin = block_min<NT>(dmin, red);
+    // the eight partial sets, each summed (min d: minimised) by thread t over
+    // t, t + NT, ... and then over the block, all in one exchange; the order
+    // is that of sum_partials / block_min
+    const int sets[8] = {PS_CHK_R, PS_CHK_X, PS_CHK_B, PS_CHK_RW, PS_CHK_DMIN, PS_CHK_BAD, PS_CHK_DIFF, PS_CHK_DSUM};
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 1.0e300, 0.0, 0.0, 0.0};
+    const auto* part = gbl(sd.part);
+    for (int i = threadIdx.x; i < npart_chk; i += NT) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const double v = part[sets[a] * stride + i];
+            acc[a] = (a == 4) ? fmin(acc[a], v) : acc[a] + v;
+        }
+    }
+    const double tot = block_reduce_n<NT, 8, 1u << 4>(acc, red);
+    if (threadIdx.x < 8) s_tot[threadIdx.x] = tot;
+    __syncthreads();
+    const double R = s_tot[0], X = s_tot[1], B = s_tot[2], RW = s_tot[3];
+    const double dmin = s_tot[4], BAD = s_tot[5], DIFF = s_tot[6], DSUM = s_tot[7];
     if (threadIdx.x == 0) {
         if (st->checks == 0) st->dbar = DSUM / (double)n;
         s_update = check_decide(st, R, X, B, RW, BAD, DIFF, dmin);
