@@ -283,6 +283,7 @@ __device__ __forceinline__ Mask2 mask2(const SlotDesc& sd, size_t idx) {
 template <typename T>
 struct ProApply {
     static constexpr int NACC = 0;
+    static constexpr bool PREF = false;
     struct Sh {};
     using Gate = GateAlways;
     static __device__ __forceinline__ bool begin(const SlotDesc&, Sh&, int, int) { return true; }
@@ -321,6 +322,46 @@ struct ProCG {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->rho_cur = rr;
         return true;
     }
+    // FP32: the pair's r, p and x correction are requested before the r.r
+    // reduction (fetch), so that the reduction's latency overlaps them; the
+    // arithmetic (combine) is the same either way
+    static constexpr bool PREF = sizeof(W) == 4;
+    struct Raw {
+        cx<W> r, p;
+        cx<XA> x;
+    };
+    static __device__ __forceinline__ XA* xacc(const SlotDesc& sd) {
+        return reinterpret_cast<XA*>(sizeof(XA) == 8 ? (void*)sd.x : (void*)sd.e);
+    }
+    template <int L>
+    static __device__ __forceinline__ Raw fetch(const SlotDesc& sd, int row, int col) {
+        const size_t idx = (size_t)row * L + col;
+        Raw w;
+        w.r = ld2<W>(reinterpret_cast<const W*>(sd.r) + idx);
+        w.p = ld2<W>(reinterpret_cast<const W*>(sd.p) + idx);
+        w.x = ld2<XA>(xacc(sd) + idx);
+        return w;
+    }
+    template <int L>
+    static __device__ __forceinline__ cx<W> combine(const SlotDesc& sd, const Sh& sh, const Raw& w, int row,
+                                                    int col, double*) {
+        const size_t idx = (size_t)row * L + col;
+        cx<W> p2;
+        if (sh.restart) {
+            p2 = w.r;
+        } else {
+            const cx<W> po = w.p;
+            p2 = mkc(w.r.x + sh.beta * po.x, w.r.y + sh.beta * po.y);
+            if (sh.alpha != W(0)) {
+                cx<XA> xv = w.x;
+                xv.x += (XA)sh.alpha * (XA)po.x;
+                xv.y += (XA)sh.alpha * (XA)po.y;
+                st2<XA>(xacc(sd) + idx, xv);
+            }
+        }
+        st2<W>(reinterpret_cast<W*>(sd.p) + idx, p2);
+        return p2;
+    }
     template <int L>
     static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col, double*) {
         const size_t idx = (size_t)row * L + col;
@@ -334,7 +375,7 @@ struct ProCG {
             cx<W> po = ld2<W>(p + idx);
             p2 = mkc(r2.x + sh.beta * po.x, r2.y + sh.beta * po.y);
             if (sh.alpha != W(0)) {
-                XA* xa = reinterpret_cast<XA*>(sizeof(XA) == 8 ? (void*)sd.x : (void*)sd.e);
+                XA* xa = xacc(sd);
                 cx<XA> xv = ld2<XA>(xa + idx);
                 xv.x += (XA)sh.alpha * (XA)po.x;
                 xv.y += (XA)sh.alpha * (XA)po.y;
@@ -351,6 +392,7 @@ struct ProCG {
 template <typename W, int NT>
 struct ProCheck {
     static constexpr int NACC = 0;
+    static constexpr bool PREF = false;
     struct Sh {
         double alpha;
         int mixed;
@@ -395,8 +437,11 @@ struct ProCheck {
 template <typename W, typename XA, int NT, int NPZ>
 struct ProPCG {
     static constexpr int NACC = 0;
+    // FP32: z, p and the x correction are requested before the reductions
+    static constexpr bool PREF = sizeof(W) == 4;
     struct Sh {
-        double red[(NT + 63) / 64];
+        double red[2 * ((NT + 63) / 64)];
+        double tot[2];
         W alpha, beta;
         int restart;
     };
@@ -404,12 +449,27 @@ struct ProPCG {
     static __device__ __forceinline__ bool begin(const SlotDesc& sd, Sh& sh, int npart_rr, int stride) {
         if (!GateIter::ok(sd)) return false;
         SolveState* st = sd.st;
-        const double rr = sum_partials<NT>(sd.part + PS_RR * stride, npart_rr, sh.red);
+        double rr, rz;
+        if constexpr (NT % 64 == 0) {
+            // r.r and r.z reduced together (each in sum_partials' order)
+            double a2[2] = {0.0, 0.0};
+            const auto* prr = gbl(sd.part + PS_RR * stride);
+            const auto* prz = gbl(sd.part + PS_RZ * stride);
+            for (int i = threadIdx.x; i < npart_rr; i += NT) a2[0] += prr[i];
+            for (int i = threadIdx.x; i < NPZ; i += NT) a2[1] += prz[i];
+            const double t = block_reduce_n<NT, 2, 0u>(a2, sh.red);
+            if (threadIdx.x < 2) sh.tot[threadIdx.x] = t;
+            __syncthreads();
+            rr = sh.tot[0];
+            rz = sh.tot[1];
+        } else {
+            rr = sum_partials<NT>(sd.part + PS_RR * stride, npart_rr, sh.red);
+            rz = sum_partials<NT>(sd.part + PS_RZ * stride, NPZ, sh.red);
+        }
         if (check_due(st, rr)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) st->pause = 1;
             return false;
         }
-        const double rz = sum_partials<NT>(sd.part + PS_RZ * stride, NPZ, sh.red);
         const int restart = st->restart;
         const double beta = restart ? 0.0 : rz / st->rho_prev;
         sh.alpha = (W)st->alpha;
@@ -420,6 +480,42 @@ struct ProPCG {
             st->need_pre = 0;
         }
         return true;
+    }
+    struct Raw {
+        cx<W> z, p;
+        cx<XA> x;
+    };
+    static __device__ __forceinline__ XA* xacc(const SlotDesc& sd) {
+        return reinterpret_cast<XA*>(sizeof(XA) == 8 ? (void*)sd.x : (void*)sd.e);
+    }
+    template <int L>
+    static __device__ __forceinline__ Raw fetch(const SlotDesc& sd, int row, int col) {
+        const size_t idx = (size_t)row * L + col;
+        Raw w;
+        w.z = ld2<W>(reinterpret_cast<const W*>(sd.z) + idx);
+        w.p = ld2<W>(reinterpret_cast<const W*>(sd.p) + idx);
+        w.x = ld2<XA>(xacc(sd) + idx);
+        return w;
+    }
+    template <int L>
+    static __device__ __forceinline__ cx<W> combine(const SlotDesc& sd, const Sh& sh, const Raw& w, int row,
+                                                    int col, double*) {
+        const size_t idx = (size_t)row * L + col;
+        cx<W> p2;
+        if (sh.restart) {
+            p2 = w.z;
+        } else {
+            const cx<W> po = w.p;
+            p2 = mkc(w.z.x + sh.beta * po.x, w.z.y + sh.beta * po.y);
+            if (sh.alpha != W(0)) {
+                cx<XA> xv = w.x;
+                xv.x += (XA)sh.alpha * (XA)po.x;
+                xv.y += (XA)sh.alpha * (XA)po.y;
+                st2<XA>(xacc(sd) + idx, xv);
+            }
+        }
+        st2<W>(reinterpret_cast<W*>(sd.p) + idx, p2);
+        return p2;
     }
     template <int L>
     static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col, double*) {
@@ -453,6 +549,7 @@ struct ProPCG {
 template <typename W, int NT, int NPQ>
 struct ProUpdPre {
     static constexpr int NACC = 1;
+    static constexpr bool PREF = sizeof(W) == 4;  // r and q requested before the p.q reduction
     static constexpr int SET = PS_RR;
     struct Sh {
         double red[(NT + 63) / 64];
@@ -494,6 +591,23 @@ struct ProUpdPre {
         acc[0] += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
         return rn;
     }
+    struct Raw {
+        cx<W> r, q;
+    };
+    template <int L>
+    static __device__ __forceinline__ Raw fetch(const SlotDesc& sd, int row, int col) {
+        const size_t idx = (size_t)row * L + col;
+        return Raw{ld2<W>(reinterpret_cast<const W*>(sd.r) + idx), ld2<W>(reinterpret_cast<const W*>(sd.q) + idx)};
+    }
+    template <int L>
+    static __device__ __forceinline__ cx<W> combine(const SlotDesc& sd, const Sh& sh, const Raw& w, int row,
+                                                    int col, double* acc) {
+        const size_t idx = (size_t)row * L + col;
+        const cx<W> rn = mkc(w.r.x - sh.alpha * w.q.x, w.r.y - sh.alpha * w.q.y);
+        st2<W>(reinterpret_cast<W*>(sd.r) + idx, rn);
+        acc[0] += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
+        return rn;
+    }
 };
 
 // Preconditioner after a check that continues the solve: transform the
@@ -501,6 +615,7 @@ struct ProUpdPre {
 template <typename W>
 struct ProPre {
     static constexpr int NACC = 0;
+    static constexpr bool PREF = false;
     struct Sh {};
     using Gate = GatePre;
     static __device__ __forceinline__ bool begin(const SlotDesc& sd, Sh&, int, int) { return GatePre::ok(sd); }
@@ -629,7 +744,6 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     __shared__ typename Pro::Sh sh;
     __shared__ double fred[(NT + 63) / 64];
     const SlotDesc& sd = slot.get();
-    if (!Pro::begin(sd, sh, npart_rr, stride)) return;
     double acc = 0.0;
     const int tid = threadIdx.x;
     const int rl = tid / P, j = tid % P;
@@ -639,14 +753,30 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     cx<T> v[E];
     constexpr int NSTG = fft_nstages(N);
     constexpr int R1 = NSTG > 0 ? fft_radix(N, false, 0) : 1;
+    constexpr int RK = PAD ? R1 / 2 : R1;  // inputs per run (the rest are known zeros on the padded grid)
+    if constexpr (Pro::PREF && (E / R1) * RK <= 8) {
+        // the inputs are requested before begin()'s reductions
+        if (!Pro::Gate::ok(sd)) return;
+        typename Pro::Raw raw[(E / R1) * RK];
 #pragma unroll
-    for (int u = 0; u < E / R1; ++u) {
+        for (int u = 0; u < E / R1; ++u)
 #pragma unroll
-        for (int r = 0; r < R1; ++r) {
-            if (PAD && r >= R1 / 2) continue;  // known zeros (padded grid)
-            const int n = (j + u * P) + r * (N / R1);
-            v[u * R1 + r] = Pro::template load2<L>(sd, sh, row, 2 * n, &acc);
-        }
+            for (int r = 0; r < RK; ++r)
+                raw[u * RK + r] = Pro::template fetch<L>(sd, row, 2 * ((j + u * P) + r * (N / R1)));
+        if (!Pro::begin(sd, sh, npart_rr, stride)) return;
+#pragma unroll
+        for (int u = 0; u < E / R1; ++u)
+#pragma unroll
+            for (int r = 0; r < RK; ++r)
+                v[u * R1 + r] = Pro::template combine<L>(sd, sh, raw[u * RK + r], row,
+                                                         2 * ((j + u * P) + r * (N / R1)), &acc);
+    } else {
+        if (!Pro::begin(sd, sh, npart_rr, stride)) return;
+#pragma unroll
+        for (int u = 0; u < E / R1; ++u)
+#pragma unroll
+            for (int r = 0; r < RK; ++r)
+                v[u * R1 + r] = Pro::template load2<L>(sd, sh, row, 2 * ((j + u * P) + r * (N / R1)), &acc);
     }
     fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
     constexpr int RL = NSTG > 0 ? fft_radix(N, false, NSTG - 1) : 1;
