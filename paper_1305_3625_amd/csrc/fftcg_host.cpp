@@ -308,15 +308,12 @@ extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) {
     return FFTCG_OK;
 }
 
-// AUTO picks the fused engine for grids of at most 64 x 64 unknowns: there
-// one workgroup per solve beats four kernel launches per iteration (measured
-// on MI355X: 19-31 us against 30-45 us per product up to L = 64); from
-// L = 128 on, the fused engine's serial rounds cost more than the launches
-// and the multi-pass engine takes over, for single solves and server classes.
-// AUTO: a single solve takes the fused engine up to M = 64; a server class,
-// whose slots share each launch of the multi-pass engine, up to M = 128
-// (measured crossovers: at M = 128 one fused solve is 15-25% slower than a
-// multi-pass one, while 64 batched solves run as fast or faster fused).
+// AUTO: one workgroup per solve beats four kernel launches per iteration on
+// the smallest grids.  A single solve takes the fused engine up to M = 64; a
+// server class, whose slots share each launch of the multi-pass engine, up
+// to M = 128 (measured crossovers: at M = 128 one fused solve is 15-25%
+// slower than a multi-pass one, while 64 batched solves run as fast or
+// faster fused; from M = 256 on the fused engine's serial rounds cost more).
 int fftcg::plan_engine(const fftcg_plan_s* p) {
     if (p->precond != FFTCG_PRECOND_NONE) return FFTCG_ENGINE_MULTIPASS;  // the fused engine has no preconditioner
     if (p->engine == FFTCG_ENGINE_AUTO)
