@@ -114,7 +114,11 @@ __device__ __forceinline__ bool check_due(const SolveState* st, double rr) {
     const bool progressed = iters > st->last_check_iter;
     const bool periodic = st->refresh > 0 && iters - st->last_check_iter >= st->refresh;
     const bool candidate = progressed && !(rr > st->trigger_rr);
-    const bool reliable = progressed && rr <= st->delta2 * st->rho_ref;
+    // a reliable update is skipped when the convergence trigger lies within
+    // a factor 100 (10 in the residual norm) below its threshold: the check at
+    // candidate convergence comes soon and replaces the residual as well
+    const double rel = st->delta2 * st->rho_ref;
+    const bool reliable = progressed && rr <= rel && st->trigger_rr < 1e-2 * rel;
     return iters >= st->maxit || candidate || periodic || reliable;
 }
 
