@@ -924,6 +924,17 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
     const int rl = tid / P, j = tid % P;
     const int row0 = xcd_remap(blockIdx.x, gridDim.x) * RPW;
     const cx<T>* Wb = reinterpret_cast<const cx<T>*>(sd.W);
+    // all of this thread's spectrum values are requested before the first
+    // is stored to LDS (more reads in flight per wave)
+    cx<T> wv[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int qi = tid + s * NT;
+        const int kk = qi % TT;
+        const int il = (qi / TT) % RPW;
+        const int kt = qi / (TT * RPW);
+        wv[s] = gld(Wb + ((size_t)kt * L + row0 + il) * TT + kk);
+    }
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int qi = tid + s * NT;
@@ -931,7 +942,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
         const int il = (qi / TT) % RPW;
         const int kt = qi / (TT * RPW);
         LdsLay<T, 1, 4, 1> l2{lds + il * WORDS, 0};
-        l2.st(kt * TT + kk, gld(Wb + ((size_t)kt * L + row0 + il) * TT + kk));
+        l2.st(kt * TT + kk, wv[s]);
     }
     __syncthreads();
     LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
