@@ -203,7 +203,9 @@ __device__ inline int check_decide(SolveState* st, double R, double X, double B,
 // ---- slot access policies -------------------------------------------------
 struct ByPtr {
     const SlotDesc* p;
-    __device__ __forceinline__ const SlotDesc& get() const { return p[blockIdx.y]; }
+    // a copy, read once: the kernels' stores cannot alias it, so its fields
+    // stay in registers instead of being read again after every store
+    __device__ __forceinline__ SlotDesc get() const { return p[blockIdx.y]; }
 };
 struct ByVal {
     SlotDesc s;
@@ -277,7 +279,7 @@ struct Mask2 {
 };
 __device__ __forceinline__ Mask2 mask2(const SlotDesc& sd, size_t idx) {
     if (!sd.mask) return Mask2{1.0, 1.0};
-    const uint8_t* m = sd.mask + idx;
+    const auto* m = gbl(sd.mask + idx);
     return Mask2{(double)m[0], (double)m[1]};
 }
 
@@ -635,6 +637,7 @@ struct ProPre {
 template <typename T>
 struct EpiApply {
     static constexpr int NACC = 0;
+    static constexpr bool PREF = false;
     using Gate = GateAlways;
     static __device__ __forceinline__ bool begin(const SlotDesc&) { return true; }
     template <int L>
@@ -654,18 +657,35 @@ struct EpiCG {
     static constexpr int SET = PS_PQ;
     using Gate = GateIter;
     static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return GateIter::ok(sd); }
+    // FP32: p and d of every output are requested before the transform, so
+    // their reads neither wait behind the q stores (which may alias them as
+    // far as the compiler knows) nor expose their latency after it
+    static constexpr bool PREF = sizeof(W) == 4;
+    struct Pre {
+        cx<W> p, d;
+    };
+    template <int L>
+    static __device__ __forceinline__ Pre pre(const SlotDesc& sd, int row, int col) {
+        const size_t idx = (size_t)row * L + col;
+        Pre v;
+        v.p = ld2<W>(reinterpret_cast<const W*>(sd.p) + idx);
+        if constexpr (sizeof(W) == 4) {
+            v.d = ld2<float>(sd.d32 + idx);
+        } else {
+            v.d = ld2<double>(sd.d + idx);
+        }
+        return v;
+    }
     template <int L>
     static __device__ __forceinline__ void out2(const SlotDesc& sd, int row, int col, W c0, W c1, double* acc) {
+        out2p<L>(sd, row, col, c0, c1, pre<L>(sd, row, col), acc);
+    }
+    template <int L>
+    static __device__ __forceinline__ void out2p(const SlotDesc& sd, int row, int col, W c0, W c1, const Pre& pr,
+                                                 double* acc) {
         const size_t idx = (size_t)row * L + col;
-        const W* p = reinterpret_cast<const W*>(sd.p);
         W* q = reinterpret_cast<W*>(sd.q);
-        cx<W> pv = ld2<W>(p + idx);
-        cx<W> dv;
-        if constexpr (sizeof(W) == 4) {
-            dv = ld2<float>(sd.d32 + idx);
-        } else {
-            dv = ld2<double>(sd.d + idx);
-        }
+        const cx<W> pv = pr.p, dv = pr.d;
         cx<W> qv = mkc(dv.x * pv.x + c0, dv.y * pv.y + c1);
         if (sd.mask) {
             const Mask2 mk = mask2(sd, idx);
@@ -682,6 +702,7 @@ struct EpiCG {
 template <typename W>
 struct EpiCheck {
     static constexpr int NACC = 8;
+    static constexpr bool PREF = false;
     using Gate = GateCheck;
     static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return GateCheck::ok(sd); }
     template <int L>
@@ -722,10 +743,23 @@ struct EpiPre {
     static constexpr int SET = PS_RZ;
     using Gate = G;
     static __device__ __forceinline__ bool begin(const SlotDesc& sd) { return G::ok(sd); }
+    static constexpr bool PREF = sizeof(W) == 4;  // r requested before the transform
+    struct Pre {
+        cx<W> r;
+    };
+    template <int L>
+    static __device__ __forceinline__ Pre pre(const SlotDesc& sd, int row, int col) {
+        return Pre{ld2<W>(reinterpret_cast<const W*>(sd.r) + (size_t)row * L + col)};
+    }
     template <int L>
     static __device__ __forceinline__ void out2(const SlotDesc& sd, int row, int col, W c0, W c1, double* acc) {
+        out2p<L>(sd, row, col, c0, c1, pre<L>(sd, row, col), acc);
+    }
+    template <int L>
+    static __device__ __forceinline__ void out2p(const SlotDesc& sd, int row, int col, W c0, W c1, const Pre& pr,
+                                                 double* acc) {
         const size_t idx = (size_t)row * L + col;
-        const cx<W> rv = ld2<W>(reinterpret_cast<const W*>(sd.r) + idx);
+        const cx<W> rv = pr.r;
         if (sd.mask) {
             const Mask2 mk = mask2(sd, idx);
             c0 *= (W)mk.m0;
@@ -734,6 +768,16 @@ struct EpiPre {
         st2<W>(reinterpret_cast<W*>(sd.z) + idx, mkc(c0, c1));
         acc[0] += (double)rv.x * (double)c0 + (double)rv.y * (double)c1;
     }
+};
+
+// Prefetched epilogue operands of an epilogue with PREF (its Pre type).
+template <class Epi, bool = Epi::PREF>
+struct EpiPreT {
+    using type = int;
+};
+template <class Epi>
+struct EpiPreT<Epi, true> {
+    using type = typename Epi::Pre;
 };
 
 // ==== kernels ==============================================================
@@ -935,6 +979,20 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
         const int kt = qi / (TT * RPW);
         wv[s] = gld(Wb + ((size_t)kt * L + row0 + il) * TT + kk);
     }
+    constexpr int NSTG = fft_nstages(N);
+    constexpr int RL = NSTG > 0 ? fft_radix(N, true, NSTG - 1) : 1;
+    constexpr int RK = (PAD && RL > 1) ? RL / 2 : RL;  // outputs kept per run (the rest are cropped)
+    const int row = row0 + rl;
+    // the epilogue's operands (Epi::PREF), requested with the spectrum
+    using PreT = typename EpiPreT<Epi>::type;
+    PreT pre[Epi::PREF ? (E / RL) * RK : 1];
+    if constexpr (Epi::PREF) {
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RK; ++r)
+                pre[u * RK + r] = Epi::template pre<L>(sd, row, 2 * ((j + u * P) + r * (N / RL)));
+    }
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int qi = tid + s * NT;
@@ -947,7 +1005,6 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
     __syncthreads();
     LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
     cx<T> v[E];
-    constexpr int NSTG = fft_nstages(N);
     constexpr int R1 = NSTG > 0 ? fft_radix(N, true, 0) : 1;
     constexpr int S1 = N / R1;
 #pragma unroll
@@ -976,19 +1033,20 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
     }
     __syncthreads();
     fft_run<T, N, M, +1, true, false>(v, lay, j, tab.tw);
-    constexpr int RL = NSTG > 0 ? fft_radix(N, true, NSTG - 1) : 1;
     double acc[Epi::NACC > 0 ? Epi::NACC : 1];
 #pragma unroll
     for (int a = 0; a < (Epi::NACC > 0 ? Epi::NACC : 1); ++a) acc[a] = 0.0;
     if constexpr (Epi::NACC > 4) acc[4] = 1.0e300;
-    const int row = row0 + rl;
 #pragma unroll
     for (int u = 0; u < E / RL; ++u)
 #pragma unroll
-        for (int r = 0; r < RL; ++r) {
-            if (PAD && RL > 1 && r >= RL / 2) continue;
+        for (int r = 0; r < RK; ++r) {
             const int n = (j + u * P) + r * (N / RL);
-            Epi::template out2<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, acc);
+            if constexpr (Epi::PREF) {
+                Epi::template out2p<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, pre[u * RK + r], acc);
+            } else {
+                Epi::template out2<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, acc);
+            }
         }
     if constexpr (Epi::NACC > 0) {
         double* part = sd.part;
