@@ -281,7 +281,15 @@ __device__ __forceinline__ void tw_apply(cx<T>* v, const cx<T>* pb) {
 // and pre holds the twiddle bases of stage S (if it has twiddles).  On exit
 // v[u R_last + r] holds position (j + u P) + r N / R_last.
 // tw[m] = exp(-2 pi i m / MTAB); DIR = -1 forward, +1 inverse.
-template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, int S, class Lay>
+//
+// Each exchange is a barrier, the writes, a barrier, the reads.  The first
+// barrier keeps the writes from overtaking the reads of the previous
+// exchange (or, with LEAD, of whatever the caller read from the buffer
+// before); it sits after the stage's arithmetic, so that waves which finished
+// their reads compute while the others still read.  The last exchange's reads
+// are therefore not fenced: a caller that writes the buffer after the
+// transform places a barrier first.
+template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, int S, class Lay, bool LEAD>
 __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j, const cx<T>* __restrict__ tw,
                                        const cx<T>* pre) {
     constexpr int E = fft_elems(N);
@@ -305,6 +313,7 @@ __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j, const cx
             for (int u = 0; u < NB2; ++u)
                 tw_load<T, R2>(nxt + u * tw_nb<R2>(), tw, ((j + u * P) & (NS2 - 1)) * STEP2);
         }
+        if constexpr (S > 0 || LEAD) __syncthreads();
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int b = j + u * P;
@@ -314,17 +323,19 @@ __device__ __forceinline__ void stages(cx<T>* v, const Lay& lay, int j, const cx
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NB2; ++u) lay.template ld_run<R2, N / R2>(j + u * P, v + u * R2);
-        __syncthreads();
-        stages<T, N, MTAB, DIR, REV, HALF_IN, S + 1, Lay>(v, lay, j, tw, nxt);
+        stages<T, N, MTAB, DIR, REV, HALF_IN, S + 1, Lay, LEAD>(v, lay, j, tw, nxt);
     }
 }
 
-// Full transform (all stages).  Length 1 is the identity.
-template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, class Lay>
+// Full transform (all stages).  Length 1 is the identity.  LEAD: the caller
+// read the LDS buffer before (its reads are fenced before the first write).
+// Returns with the last exchange's reads unfenced (see stages).
+template <typename T, int N, int MTAB, int DIR, bool REV, bool HALF_IN, class Lay, bool LEAD = false>
 __device__ __forceinline__ void fft_run(cx<T>* v, const Lay& lay, int j,
                                         const cx<T>* __restrict__ tw) {
     // stage 0 has no twiddles (NS = 1)
-    if constexpr (fft_nstages(N) > 0) stages<T, N, MTAB, DIR, REV, HALF_IN, 0, Lay>(v, lay, j, tw, nullptr);
+    if constexpr (fft_nstages(N) > 0)
+        stages<T, N, MTAB, DIR, REV, HALF_IN, 0, Lay, LEAD>(v, lay, j, tw, nullptr);
 }
 
 // ---- reductions -----------------------------------------------------------

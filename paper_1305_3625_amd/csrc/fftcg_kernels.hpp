@@ -828,6 +828,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     }
     fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
     constexpr int RL = NSTG > 0 ? fft_radix(N, false, NSTG - 1) : 1;
+    if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
 #pragma unroll
     for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, N / RL>(j + u * P, v + u * RL);
     __syncthreads();
@@ -915,6 +916,7 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
         // packed column 0 carries k = 0 (real part) and k = M/2 (imaginary
         // part): result(m) = s(m) W(m) + t(m) conj(W(M - m)),
         // s = (g0 + gN)/2, t = (g0 - gN)/2.
+        if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
 #pragma unroll
         for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, M / RL>(j + u * P, v + u * RL);
         __syncthreads();
@@ -942,7 +944,8 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
 #pragma unroll
             for (int r = 0; r < RL; ++r) v[u * RL + r] = scalec(v[u * RL + r], gpre[u * RL + r]);
     }
-    fft_run<T, M, M, +1, true, false>(v, lay, j, tab.tw);
+    // the forward transform's (or column 0's) reads of the buffer came before
+    fft_run<T, M, M, +1, true, false, Lay, true>(v, lay, j, tab.tw);
     constexpr int RZ = fft_radix(M, true, NSTG - 1);
 #pragma unroll
     for (int u = 0; u < E / RZ; ++u)

@@ -95,6 +95,7 @@ __device__ __forceinline__ void fz_rows_fwd(cx<T>* lds, cx<T>* W, const cx<T>* _
                 v[u * R1 + r] = act ? ld(row, 2 * n) : mkc(T(0), T(0));
             }
         fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, twr);
+        if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
 #pragma unroll
         for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, N / RL>(j + u * P, v + u * RL);
         __syncthreads();
@@ -155,6 +156,7 @@ __device__ __forceinline__ void fz_cols(cx<T>* lds, cx<T>* W, const cx<T>* __res
         const bool col0 = rd == 0 && cl == 0;
         if (rd == 0) {
             // column 0 needs Y(M - m) from other threads of its group
+            if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
 #pragma unroll
             for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, M / RL>(j + u * P, v + u * RL);
             __syncthreads();
@@ -184,7 +186,8 @@ __device__ __forceinline__ void fz_cols(cx<T>* lds, cx<T>* W, const cx<T>* __res
                     v[u * RL + r] = scalec(v[u * RL + r], *gbl(gqr + mp * MH + c));
                 }
         }
-        fft_run<T, M, M, +1, true, false>(v, lay, j, opaque(twr));
+        // the forward transform's (or column 0's) reads of the buffer came before
+        fft_run<T, M, M, +1, true, false, LdsLay<T, 1, 4, 1>, true>(v, lay, j, opaque(twr));
         if (act) {
 #pragma unroll
             for (int u = 0; u < E / RZ; ++u)
