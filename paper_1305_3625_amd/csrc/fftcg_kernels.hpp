@@ -983,6 +983,14 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
         wv[s] = gld(Wb + ((size_t)kt * L + row0 + il) * TT + kk);
     }
     constexpr int NSTG = fft_nstages(N);
+    constexpr int R1 = NSTG > 0 ? fft_radix(N, true, 0) : 1;
+    constexpr int S1 = N / R1;
+    // the unpack's twiddles, requested with the spectrum (before the barrier)
+    cx<T> twk[E];
+#pragma unroll
+    for (int u = 0; u < E / R1; ++u)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) twk[u * R1 + r] = gld(tab.tw + (j + u * P) + r * S1);
     constexpr int RL = NSTG > 0 ? fft_radix(N, true, NSTG - 1) : 1;
     constexpr int RK = (PAD && RL > 1) ? RL / 2 : RL;  // outputs kept per run (the rest are cropped)
     const int row = row0 + rl;
@@ -1008,8 +1016,6 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
     __syncthreads();
     LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
     cx<T> v[E];
-    constexpr int R1 = NSTG > 0 ? fft_radix(N, true, 0) : 1;
-    constexpr int S1 = N / R1;
 #pragma unroll
     for (int u = 0; u < E / R1; ++u) {
         // Y at k = jj + r S1, and the partners N - k = (S1 - jj) + (R1-1-r) S1
@@ -1028,7 +1034,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
             } else {
                 const cx<T> B = conjc(jj == 0 ? Bv[(R1 - r) % R1] : Bv[R1 - 1 - r]);
                 const cx<T> s1 = Y + B, d1 = Y - B;
-                const cx<T> wd = cmul(conjc(tab.tw[k]), d1);
+                const cx<T> wd = cmul(conjc(twk[u * R1 + r]), d1);
                 Z = mkc(s1.x - wd.y, s1.y + wd.x);
             }
             v[u * R1 + r] = Z;
