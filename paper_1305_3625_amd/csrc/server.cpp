@@ -78,7 +78,7 @@ struct Slot {
     double* t = nullptr;
     int* broken = nullptr;            // device, one entry per step
     SolveState* pin_state = nullptr;  // pinned staging of the state
-    double* stage = nullptr;          // pinned staging of pageable request inputs
+    double* stage = nullptr;          // pinned staging of pageable request inputs (on first use)
     Request* req = nullptr;
     int gen = 0;
     int step = 0;
@@ -195,7 +195,6 @@ bool add_slot(fftcg_server_s* srv, Class* c) {
          hipMalloc(&s->d, n * 8) == hipSuccess && hipMalloc(&s->t, n * 8) == hipSuccess &&
          hipMalloc(&s->broken, sizeof(int) * kMaxSteps) == hipSuccess &&
          hipHostMalloc((void**)&s->pin_state, sizeof(SolveState), hipHostMallocDefault) == hipSuccess &&
-         hipHostMalloc((void**)&s->stage, n * 8 * 4, hipHostMallocDefault) == hipSuccess &&
          hipEventCreateWithFlags(&s->ev_retire, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         free_slot_memory(s.get());
@@ -275,9 +274,18 @@ void admit(Class* c, Request* q, int idx) {
     if (!q->in_pinned) {
         // pageable inputs go through the slot's pinned staging buffer (free:
         // its previous request was admitted, and its copies done, before it
-        // retired)
-        memcpy(s->stage, q->pin_in, q->in_bytes);
-        pin = s->stage;
+        // retired), allocated the first time a slot needs it: pinning costs
+        // milliseconds, and slots fed from the pinned pool never need one.
+        // Without it the copies read the pageable buffer, which stays alive
+        // until the request is polled.
+        if (!s->stage && hipHostMalloc((void**)&s->stage, n * 8 * 4, hipHostMallocDefault) != hipSuccess) {
+            s->stage = nullptr;
+            (void)hipGetLastError();  // the failure is handled here
+        }
+        if (s->stage) {
+            memcpy(s->stage, q->pin_in, q->in_bytes);
+            pin = s->stage;
+        }
     }
     hipStream_t st = c->stream;
     (void)hipMemcpyAsync(s->d, pin, n * 8, hipMemcpyHostToDevice, st);
@@ -408,12 +416,15 @@ bool progress(fftcg_server_s* srv, Class* c) {
         srv->in_flight.fetch_add(1);
         admit(c, q, idx);
     }
-    // one chunk over all slots of the class when any solve is running
-    bool active = false;
-    for (auto& s : c->slots)
-        if (s->req && !s->retiring) active = true;
+    // one chunk over the slots of the class up to the last running one (new
+    // requests take the lowest free slot, so a pool grown by a burst costs
+    // nothing once the burst is over) when any solve is running
+    int last = -1;
+    for (int i = 0; i < (int)c->slots.size(); ++i)
+        if (c->slots[i]->req && !c->slots[i]->retiring) last = i;
+    const bool active = last >= 0;
     if (active && c->inflight < 2) {
-        const int nsl = (int)c->slots.size();
+        const int nsl = last + 1;
         if (server_engine(c->plan) == FFTCG_ENGINE_FUSED) {
             // one workgroup per slot runs the chunk's iterations and checks
             fused_launch(c->plan, c->precision, c->d_table, nsl, srv->opts.chunk_iters, c->stream);
