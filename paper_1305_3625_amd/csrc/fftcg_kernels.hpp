@@ -919,19 +919,29 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
         if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
 #pragma unroll
         for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, M / RL>(j + u * P, v + u * RL);
+        // this thread's values of the spectrum's column M/2, read together
+        // (inside the per-element branch below each read would wait for the
+        // previous element)
+        T gN[E];
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int m = (j + u * P) + r * (M / RL);
+                gN[u * RL + r] = tab.ghN[m <= M - m ? m : M - m];
+            }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < E / RL; ++u)
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int m = (j + u * P) + r * (M / RL);
-                const int mp = m <= M - m ? m : M - m;
                 const cx<T> a = v[u * RL + r];
                 if (kk == 0) {
                     const cx<T> bm = conjc(lay.ld((M - m) & (M - 1)));
                     const T g0 = gpre[u * RL + r];
-                    const T gN = PRE ? pre_mul(tab.ghN[mp], c2, c4) : tab.ghN[mp];
-                    const T s = T(0.5) * (g0 + gN), t = T(0.5) * (g0 - gN);
+                    const T gNv = PRE ? pre_mul(gN[u * RL + r], c2, c4) : gN[u * RL + r];
+                    const T s = T(0.5) * (g0 + gNv), t = T(0.5) * (g0 - gNv);
                     v[u * RL + r] = mkc(s * a.x + t * bm.x, s * a.y + t * bm.y);
                 } else {
                     v[u * RL + r] = scalec(a, gpre[u * RL + r]);
