@@ -67,11 +67,15 @@ struct FGeo {
     static_assert(PR <= FNT && PC <= FNT, "one row and one column fit a workgroup");
 };
 
-// Forward row pass: row i of the input (packed pairs from ld) -> column-major
-// half spectrum W[k L + i], k in [0, N); column 0 carries k = 0 and k = N in
-// its real and imaginary parts.
-template <typename T, int M, int PAD, class LD>
-__device__ __forceinline__ void fz_rows_fwd(cx<T>* lds, cx<T>* W, const cx<T>* __restrict__ tw, LD ld) {
+// Forward row pass: row i of the input -> column-major half spectrum
+// W[k L + i], k in [0, N); column 0 carries k = 0 and k = N in its real and
+// imaginary parts.  The input pairs come in two steps: ldf(i, col) reads
+// what a pair needs, ldc(raw, i, col) combines (and stores what the gather
+// updates) and returns the pair.  All of a thread's reads come first: a
+// store of one pair would otherwise hold up the reads of the next.
+template <typename T, int M, int PAD, class LDF, class LDC>
+__device__ __forceinline__ void fz_rows_fwd(cx<T>* lds, cx<T>* W, const cx<T>* __restrict__ tw, LDF ldf,
+                                            LDC ldc) {
     using G = FGeo<T, M, PAD>;
     constexpr int N = G::N, E = G::ER, P = G::PR, L = G::L;
     constexpr int NSTG = fft_nstages(N);
@@ -86,14 +90,22 @@ __device__ __forceinline__ void fz_rows_fwd(cx<T>* lds, cx<T>* W, const cx<T>* _
         const cx<T>* twr = opaque(tw);
         cx<T>* Wr = opaque(W);
         cx<T> v[E];
+        constexpr int RK = PAD ? R1 / 2 : R1;  // inputs per run (the rest are known zeros on the padded grid)
+        if (act) {
+            decltype(ldf(0, 0)) raw[(E / R1) * RK];
 #pragma unroll
-        for (int u = 0; u < E / R1; ++u)
+            for (int u = 0; u < E / R1; ++u)
 #pragma unroll
-            for (int r = 0; r < R1; ++r) {
-                if (PAD && r >= R1 / 2) continue;  // known zeros (padded grid)
-                const int n = (j + u * P) + r * (N / R1);
-                v[u * R1 + r] = act ? ld(row, 2 * n) : mkc(T(0), T(0));
-            }
+                for (int r = 0; r < RK; ++r) raw[u * RK + r] = ldf(row, 2 * ((j + u * P) + r * (N / R1)));
+#pragma unroll
+            for (int u = 0; u < E / R1; ++u)
+#pragma unroll
+                for (int r = 0; r < RK; ++r)
+                    v[u * R1 + r] = ldc(raw[u * RK + r], row, 2 * ((j + u * P) + r * (N / R1)));
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = mkc(T(0), T(0));
+        }
         fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, twr);
         if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
 #pragma unroll
@@ -203,10 +215,12 @@ __device__ __forceinline__ void fz_cols(cx<T>* lds, cx<T>* W, const cx<T>* __res
 }
 
 // Inverse row pass: complex-to-real pack of row i of W (partners N - k read
-// from W directly), inverse transform, and st(i, col, c0, c1) with the
-// convolution values at columns col, col + 1 (< L).
-template <typename T, int M, int PAD, class ST>
-__device__ __forceinline__ void fz_rows_inv(cx<T>* lds, const cx<T>* W, const cx<T>* __restrict__ tw, ST st) {
+// from W directly), inverse transform, and the epilogue with the
+// convolution values c0, c1 at columns col, col + 1 (< L), again in two
+// steps: stf(i, col) reads the operands, stc(raw, i, col, c0, c1) finishes.
+template <typename T, int M, int PAD, class STF, class STC>
+__device__ __forceinline__ void fz_rows_inv(cx<T>* lds, const cx<T>* W, const cx<T>* __restrict__ tw, STF stf,
+                                            STC stc) {
     using G = FGeo<T, M, PAD>;
     constexpr int N = G::N, E = G::ER, P = G::PR, L = G::L;
     constexpr int NSTG = fft_nstages(N);
@@ -223,45 +237,95 @@ __device__ __forceinline__ void fz_rows_inv(cx<T>* lds, const cx<T>* W, const cx
         const cx<T>* twr = opaque(tw);
         const cx<T>* Wr = opaque(W);
         cx<T> v[E];
+        // with up to 8 values per thread, the pairs, partners and twiddles
+        // are all read before the first unpack (one wait instead of one per
+        // value behind its branch); larger counts keep the registers
+        constexpr bool HOIST = E <= 8;
+        cx<T> Yh[HOIST ? E : 1], Bh[HOIST ? E : 1], Th[HOIST ? E : 1];
+        if constexpr (HOIST) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int k = (j + (i / R1) * P) + (i % R1) * S1;
+                Yh[i] = gld(Wr + k * L + ri);
+                Bh[i] = gld(Wr + ((N - k) & (N - 1)) * L + ri);  // k = 0: unused
+                Th[i] = gld(twr + k);
+            }
+        }
 #pragma unroll
         for (int u = 0; u < E / R1; ++u)
 #pragma unroll
             for (int r = 0; r < R1; ++r) {
                 const int k = (j + u * P) + r * S1;
-                const cx<T> Y = gld(Wr + k * L + ri);
+                const int i = u * R1 + r;
+                const cx<T> Y = [&] {
+                    if constexpr (HOIST) return Yh[i]; else return gld(Wr + k * L + ri);
+                }();
                 cx<T> Z;
                 if (k == 0) {
                     Z = mkc(Y.x + Y.y, Y.x - Y.y);
                 } else {
-                    const cx<T> B = conjc(gld(Wr + (N - k) * L + ri));
+                    const cx<T> B = conjc([&] {
+                        if constexpr (HOIST) return Bh[i]; else return gld(Wr + (N - k) * L + ri);
+                    }());
+                    const cx<T> Tk = [&] {
+                        if constexpr (HOIST) return Th[i]; else return gld(twr + k);
+                    }();
                     const cx<T> s1 = Y + B, d1 = Y - B;
-                    const cx<T> wd = cmul(conjc(gld(twr + k)), d1);
+                    const cx<T> wd = cmul(conjc(Tk), d1);
                     Z = mkc(s1.x - wd.y, s1.y + wd.x);
                 }
-                v[u * R1 + r] = Z;
+                v[i] = Z;
             }
         fft_run<T, N, M, +1, true, false>(v, lay, j, opaque(twr));
         if (act) {
+            constexpr int RK = (PAD && RL > 1) ? RL / 2 : RL;  // columns >= L are cropped
+            decltype(stf(0, 0)) raw[(E / RL) * RK];
 #pragma unroll
             for (int u = 0; u < E / RL; ++u)
 #pragma unroll
-                for (int r = 0; r < RL; ++r) {
-                    if (PAD && RL > 1 && r >= RL / 2) continue;  // columns >= L are cropped
-                    const int n = (j + u * P) + r * (N / RL);
-                    st(row, 2 * n, v[u * RL + r].x, v[u * RL + r].y);
-                }
+                for (int r = 0; r < RK; ++r) raw[u * RK + r] = stf(row, 2 * ((j + u * P) + r * (N / RL)));
+#pragma unroll
+            for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+                for (int r = 0; r < RK; ++r)
+                    stc(raw[u * RK + r], row, 2 * ((j + u * P) + r * (N / RL)), v[u * RL + r].x,
+                        v[u * RL + r].y);
         }
         __syncthreads();
     }
 }
 
-// C v (with the caller's element-wise epilogue in st) for one slot.
-template <typename T, int M, int PAD, class LD, class ST>
-__device__ __forceinline__ void fz_product(cx<T>* lds, cx<T>* W, const cx<T>* tw, const T* gq, LD ld, ST st) {
-    fz_rows_fwd<T, M, PAD>(lds, W, tw, ld);
+// C v (with the caller's gather and element-wise epilogue, each in two
+// steps) for one slot.
+template <typename T, int M, int PAD, class LDF, class LDC, class STF, class STC>
+__device__ __forceinline__ void fz_product(cx<T>* lds, cx<T>* W, const cx<T>* tw, const T* gq, LDF ldf, LDC ldc,
+                                           STF stf, STC stc) {
+    fz_rows_fwd<T, M, PAD>(lds, W, tw, ldf, ldc);
     fz_cols<T, M, PAD>(lds, W, tw, gq);
-    fz_rows_inv<T, M, PAD>(lds, W, tw, st);
+    fz_rows_inv<T, M, PAD>(lds, W, tw, stf, stc);
 }
+
+// Operands read in the first step of the two-step gathers and epilogues.
+template <typename Wp>
+struct ChkIn {  // FP64 check gather: x, e, p
+    cx<double> x, e;
+    cx<Wp> p;
+};
+template <typename Wp>
+struct ChkOut {  // FP64 check epilogue: x, b, d, the recursive r
+    cx<double> x, b, d;
+    cx<Wp> r;
+};
+template <typename Wp>
+struct IterIn {  // iteration gather: r, p, and e (FP32) or x (FP64)
+    cx<Wp> r, p;
+    cx<Wp> xa;
+};
+template <typename Wp>
+struct IterOut {  // iteration epilogue: p, d
+    cx<Wp> p;
+    cx<double> d;
+};
 
 template <int M, int PAD>
 struct FLds {
@@ -315,26 +379,33 @@ __global__ void __launch_bounds__(FNT) k_fused_solve(FusedTabs ft, const SlotDes
             fz_product<double, M, PAD>(
                 reinterpret_cast<cx<double>*>(lds_raw), reinterpret_cast<cx<double>*>(sd.W), tw64, gq64,
                 [&](int i, int c) {
+                    // x, the correction e and p (every buffer of a slot exists)
+                    const int idx = i * L + c;
+                    return ChkIn<Wp>{ld2(x + idx), ld2f(e + idx), ld2(p + idx)};
+                },
+                [&](const ChkIn<Wp>& w, int i, int c) {
                     // x <- x + e + alpha p, e <- 0 (each pair is gathered once)
                     const int idx = i * L + c;
-                    cx<double> xv = ld2(x + idx);
+                    cx<double> xv = w.x;
                     if (mixed) {
-                        const cx<double> ev = ld2f(e + idx);
-                        xv = xv + ev;
+                        xv = xv + w.e;
                         st2(e + idx, mkc(0.0f, 0.0f));
                     }
                     if (alpha != 0.0) {
-                        const cx<Wp> pv = ld2(p + idx);
-                        xv.x += alpha * (double)pv.x;
-                        xv.y += alpha * (double)pv.y;
+                        xv.x += alpha * (double)w.p.x;
+                        xv.y += alpha * (double)w.p.y;
                     }
                     st2(x + idx, xv);
                     return xv;
                 },
-                [&](int i, int c, double c0, double c1) {
+                [&](int i, int c) {
                     const int idx = i * L + c;
-                    const cx<double> x2 = ld2(x + idx), b2 = ld2(b + idx), d2 = ld2(d + idx);
-                    const cx<Wp> ro = ld2(r + idx);
+                    return ChkOut<Wp>{ld2(x + idx), ld2(b + idx), ld2(d + idx), ld2(r + idx)};
+                },
+                [&](const ChkOut<Wp>& o, int i, int c, double c0, double c1) {
+                    const int idx = i * L + c;
+                    const cx<double> x2 = o.x, b2 = o.b, d2 = o.d;
+                    const cx<Wp> ro = o.r;
                     const double xv[2] = {x2.x, x2.y}, bv[2] = {b2.x, b2.y}, dv[2] = {d2.x, d2.y};
                     const double cv[2] = {c0, c1}, rold[2] = {(double)ro.x, (double)ro.y};
                     Wp w[2];
@@ -382,22 +453,36 @@ __global__ void __launch_bounds__(FNT) k_fused_solve(FusedTabs ft, const SlotDes
         fz_product<Wp, M, PAD>(
             reinterpret_cast<cx<Wp>*>(lds_raw), reinterpret_cast<cx<Wp>*>(sd.W), tww, gqw,
             [&](int i, int c) {
+                // r, p and the pending x update's target: the FP32 correction
+                // e when the iterations run in FP32, else x itself
+                const int idx = i * L + c;
+                IterIn<Wp> w;
+                w.r = ld2(r + idx);
+                w.p = ld2(p + idx);
+                if constexpr (sizeof(Wp) == 4) {
+                    w.xa = ld2(e + idx);
+                } else {
+                    w.xa = ld2(x + idx);
+                }
+                return w;
+            },
+            [&](const IterIn<Wp>& w, int i, int c) {
                 // p <- r + beta p (p <- r on restart), with the pending
                 // x += alpha p_old (FP64 x, or the FP32 correction e)
                 const int idx = i * L + c;
-                const cx<Wp> r2 = ld2(r + idx);
+                const cx<Wp> r2 = w.r;
                 cx<Wp> p2 = r2;
                 if (!restart) {
-                    const cx<Wp> po = ld2(p + idx);
+                    const cx<Wp> po = w.p;
                     p2 = mkc(r2.x + beta_w * po.x, r2.y + beta_w * po.y);
                     if (alpha_old != 0.0) {
-                        if (mixed) {
-                            cx<float> ev = ld2(e + idx);
+                        if constexpr (sizeof(Wp) == 4) {
+                            cx<float> ev = w.xa;
                             ev.x += (float)alpha_w * (float)po.x;
                             ev.y += (float)alpha_w * (float)po.y;
                             st2(e + idx, ev);
                         } else {
-                            cx<double> xv = ld2(x + idx);
+                            cx<double> xv = w.xa;
                             xv.x += alpha_old * (double)po.x;
                             xv.y += alpha_old * (double)po.y;
                             st2(x + idx, xv);
@@ -407,10 +492,14 @@ __global__ void __launch_bounds__(FNT) k_fused_solve(FusedTabs ft, const SlotDes
                 st2(p + idx, p2);
                 return p2;
             },
-            [&](int i, int c, Wp c0, Wp c1) {
+            [&](int i, int c) {
                 const int idx = i * L + c;
-                const cx<Wp> pv = ld2(p + idx);
-                const cx<double> dv = ld2(d + idx);
+                return IterOut<Wp>{ld2(p + idx), ld2(d + idx)};
+            },
+            [&](const IterOut<Wp>& w, int i, int c, Wp c0, Wp c1) {
+                const int idx = i * L + c;
+                const cx<Wp> pv = w.p;
+                const cx<double> dv = w.d;
                 const cx<Wp> qv = mkc((Wp)dv.x * pv.x + c0, (Wp)dv.y * pv.y + c1);
                 st2(q + idx, qv);
                 pqa += (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
@@ -427,7 +516,8 @@ __global__ void __launch_bounds__(FNT) k_fused_solve(FusedTabs ft, const SlotDes
         const double alpha = rr / pq;
         const Wp aw = (Wp)alpha;
         double acc = 0.0;
-        constexpr int UNR = 4;
+        // the pairs of r and q this thread updates are read in one go (up to 8)
+        constexpr int UNR = cmax(1, cmin(8, n / (2 * FNT)));
 #pragma unroll 1
         for (int i0 = 2 * threadIdx.x; i0 < n; i0 += 2 * FNT * UNR) {
             cx<Wp> rv[UNR], qv[UNR];
@@ -479,15 +569,15 @@ __global__ void __launch_bounds__(FNT) k_fused_apply(FusedTabs ft, const double*
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? ft.tw64 : ft.tw32);
     const T* gq = reinterpret_cast<const T*>(sizeof(T) == 8 ? ft.gq64 : ft.gq32);
     fz_product<T, M, PAD>(
-        lds, reinterpret_cast<cx<T>*>(Wbuf), tw, gq,
+        lds, reinterpret_cast<cx<T>*>(Wbuf), tw, gq, [&](int i, int c) { return ld2(x + i * L + c); },
+        [&](const cx<double>& v, int, int) { return mkc((T)v.x, (T)v.y); },
         [&](int i, int c) {
-            const cx<double> v = ld2(x + i * L + c);
-            return mkc((T)v.x, (T)v.y);
-        },
-        [&](int i, int c, T c0, T c1) {
             const int idx = i * L + c;
-            const cx<double> dv = ld2(d + idx), xv = ld2(x + idx);
-            st2(y + idx, mkc(dv.x * xv.x + (double)c0, dv.y * xv.y + (double)c1));
+            return ChkIn<double>{ld2(d + idx), ld2(x + idx), mkc(0.0, 0.0)};  // d, x
+        },
+        [&](const ChkIn<double>& w, int i, int c, T c0, T c1) {
+            const cx<double> dv = w.x, xv = w.e;
+            st2(y + i * L + c, mkc(dv.x * xv.x + (double)c0, dv.y * xv.y + (double)c1));
         });
 }
 
