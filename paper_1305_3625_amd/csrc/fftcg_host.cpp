@@ -522,6 +522,41 @@ static void fill_info(fftcg_info* info, const SolveState& st, float ms) {
     info->device_ms = ms;
 }
 
+// Chunk lengths of a single solve.  Each chunk is K iterations followed by
+// an FP64-check sequence; a check that falls due inside a chunk leaves the
+// rest of its iterations idle, and a check sequence with no check due does
+// nothing, so chunks should end where the next check falls due.  Checks come
+// at roughly even intervals (a residual replacement each time r.r has fallen
+// by a fixed factor, or every refresh iterations), so the next one is
+// expected one interval after the last.  The host sees the iteration count
+// and last check of the chunk before the one in flight.
+struct ChunkPlanner {
+    int kmax;
+    int known_iters = 0;  // iterations at the end of the last chunk the host has seen
+    int last_check = 0;   // iteration of the last check seen (the first is at 0)
+    int period = 0;       // last interval between checks, 0 = none seen yet
+    int k_prev = 0;       // length of the chunk in flight
+    explicit ChunkPlanner(int km) : kmax(km) {}
+    int next() {
+        int k = kmax;
+        if (period > 0) {
+            const int start = known_iters + k_prev;  // expected start of this chunk
+            const int due = last_check + period;
+            // up to two nominal chunks while the next check is far off
+            k = due > start ? std::min(2 * kmax, due - start) : 2;
+        }
+        k_prev = k;
+        return k;
+    }
+    void observe(int iters, int check_iter) {
+        known_iters = iters;
+        if (check_iter > last_check) {
+            period = check_iter - last_check;
+            last_check = check_iter;
+        }
+    }
+};
+
 static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, const double* b, const double* x0,
                            double tol, int maxit, double* x, fftcg_info* info, hipStream_t s,
                            const uint8_t* mask = nullptr) {
@@ -534,8 +569,7 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
         fill_slot(w->h_slot, w, x, b, d);
         w->h_slot->mask = mask;
         init_state(w->h_state, plan, precision, tol, maxit, 50);
-        w->h_status[0] = 0;
-        w->h_status[1] = 0;
+        for (int i = 0; i < 4; ++i) w->h_status[i] = 0;
         if (hipMemcpyAsync(w->slot, w->h_slot, sizeof(SlotDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(w->st, w->h_state, sizeof(SolveState), hipMemcpyHostToDevice, s) != hipSuccess) {
             rc = FFTCG_EDEVICE;
@@ -566,11 +600,13 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
         first(precision, plan->tabs, w->slot, 1, plan->stride, s);
         // preconditioned solves check every few iterations (they converge in
         // tens): shorter chunks leave fewer iterations idle behind a check
-        const int K = pcg ? std::max(2, chunk_iters_for(plan->L) / 2) : chunk_iters_for(plan->L);
-        const long max_chunks = (long)maxit + 64;
+        const int kmax = pcg ? std::max(2, chunk_iters_for(plan->L) / 2) : chunk_iters_for(plan->L);
+        const long max_chunks = 2 * (long)maxit + 64;
+        ChunkPlanner planner(kmax);
         long c = 0;
         bool finished = false;
         while (!finished) {
+            const int K = planner.next();
             for (int k = 0; k < K; ++k) iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
             check(precision, plan->tabs, w->slot, 1, plan->stride, s);
             if (hipGetLastError() != hipSuccess || hipEventRecord(w->ev[c & 1], s) != hipSuccess) {
@@ -583,6 +619,8 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
                     break;
                 }
                 if (__atomic_load_n(&w->h_status[0], __ATOMIC_ACQUIRE)) finished = true;
+                planner.observe(__atomic_load_n(&w->h_status[3], __ATOMIC_RELAXED),
+                                __atomic_load_n(&w->h_status[2], __ATOMIC_RELAXED));
             }
             ++c;
             if (c > max_chunks) {

@@ -88,14 +88,17 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return (b & 7) * (G >> 3) + (b >> 3);
 }
 
-// Status words for the host (pinned, device-visible): [1] status, [3]
-// iterations, then [0] = 2 * generation + done with release order.  Done and
-// the solve's generation travel in one word, so a host polling a reused slot
-// can never pair a stale done of the previous occupant with the new
-// generation; a host that sees done also sees the status.
-__device__ __forceinline__ void publish_status(const SlotDesc& sd, int done, int status, int gen, int iters) {
+// Status words for the host (pinned, device-visible): [1] status, [2] the
+// iteration of the last FP64 check, [3] iterations, then [0] = 2 *
+// generation + done with release order.  Done and the solve's generation
+// travel in one word, so a host polling a reused slot can never pair a stale
+// done of the previous occupant with the new generation; a host that sees
+// done also sees the status.
+__device__ __forceinline__ void publish_status(const SlotDesc& sd, int done, int status, int gen, int iters,
+                                               int last_check) {
     if (!sd.host_status) return;
     __hip_atomic_store(sd.host_status + 1, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(sd.host_status + 2, last_check, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(sd.host_status + 3, iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(sd.host_status, 2 * gen + (done ? 1 : 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -571,7 +574,7 @@ struct ProUpdPre {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 st->status = ST_EBREAKDOWN;
                 st->done = 1;
-                publish_status(sd, 1, ST_EBREAKDOWN, st->gen, st->iters);
+                publish_status(sd, 1, ST_EBREAKDOWN, st->gen, st->iters, st->last_check_iter);
             }
             return false;
         }
@@ -1124,7 +1127,7 @@ __global__ void __launch_bounds__(NT) k_update(ByPtr slot, int n, int npart_pq, 
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->status = ST_EBREAKDOWN;
             st->done = 1;
-            publish_status(sd, 1, ST_EBREAKDOWN, st->gen, st->iters);
+            publish_status(sd, 1, ST_EBREAKDOWN, st->gen, st->iters, st->last_check_iter);
         }
         return;
     }
@@ -1207,7 +1210,7 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
     if (!sd.active) return;
     SolveState* st = sd.st;
     if (st->done || !st->pause) {
-        if (threadIdx.x == 0) publish_status(sd, st->done, st->status, st->gen, st->iters);
+        if (threadIdx.x == 0) publish_status(sd, st->done, st->status, st->gen, st->iters, st->last_check_iter);
         return;
     }
     // the eight partial sets, each summed (min d: minimised) by thread t over
@@ -1233,7 +1236,7 @@ __global__ void __launch_bounds__(NT) k_check_final(ByPtr slot, int npart_chk, i
         s_update = check_decide(st, R, X, B, RW, BAD, DIFF, dmin);
         // preconditioned CG: z = P^{-1} r of the replaced residual comes next
         st->need_pre = (s_update && st->pcg) ? 1 : 0;
-        publish_status(sd, st->done, st->status, st->gen, st->iters);
+        publish_status(sd, st->done, st->status, st->gen, st->iters, st->last_check_iter);
     }
     __syncthreads();
     if (s_update) {

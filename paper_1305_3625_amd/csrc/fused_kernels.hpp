@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(FNT) k_fused_solve(FusedTabs ft, const SlotDes
     if (threadIdx.x == 0) st = *sd.st;
     __syncthreads();
     if (st.done) {
-        if (threadIdx.x == 0) publish_status(sd, st.done, st.status, st.gen, st.iters);
+        if (threadIdx.x == 0) publish_status(sd, st.done, st.status, st.gen, st.iters, st.last_check_iter);
         return;
     }
     double* x = sd.x;
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(FNT) k_fused_solve(FusedTabs ft, const SlotDes
     if (threadIdx.x == 0) {
         st.rho_cur = rr;  // carried to the next launch
         *sd.st = st;
-        publish_status(sd, st.done, st.status, st.gen, st.iters);
+        publish_status(sd, st.done, st.status, st.gen, st.iters, st.last_check_iter);
     }
 }
 
