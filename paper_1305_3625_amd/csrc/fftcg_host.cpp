@@ -529,14 +529,16 @@ static void fill_info(fftcg_info* info, const SolveState& st, float ms) {
 // at roughly even intervals (a residual replacement each time r.r has fallen
 // by a fixed factor, or every refresh iterations), so the next one is
 // expected one interval after the last.  The host sees the iteration count
-// and last check of the chunk before the one in flight.
+// and last check of the chunk before the one in flight.  Until a solve has
+// seen an interval of its own it takes the one the previous solve on the
+// same workspace ended with (solves on one plan tend to be alike).
 struct ChunkPlanner {
     int kmax;
     int known_iters = 0;  // iterations at the end of the last chunk the host has seen
     int last_check = 0;   // iteration of the last check seen (the first is at 0)
     int period = 0;       // last interval between checks, 0 = none seen yet
     int k_prev = 0;       // length of the chunk in flight
-    explicit ChunkPlanner(int km) : kmax(km) {}
+    ChunkPlanner(int km, int guess) : kmax(km), period(guess) {}
     int next() {
         int k = kmax;
         if (period > 0) {
@@ -602,7 +604,11 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
         // tens): shorter chunks leave fewer iterations idle behind a check
         const int kmax = pcg ? std::max(2, chunk_iters_for(plan->L) / 2) : chunk_iters_for(plan->L);
         const long max_chunks = 2 * (long)maxit + 64;
-        ChunkPlanner planner(kmax);
+        // (mixed precision only: an FP64 solve's one interval is its whole
+        // length, a poor guess for the next solve)
+        const int pkey = 2 * precision + (pcg ? 1 : 0);
+        const bool carry = precision == FFTCG_MIXED && w->check_period_prec == pkey;
+        ChunkPlanner planner(kmax, carry ? w->check_period : 0);
         long c = 0;
         bool finished = false;
         while (!finished) {
@@ -629,6 +635,8 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
             }
         }
         if (rc != FFTCG_OK) break;
+        w->check_period = planner.period;
+        w->check_period_prec = pkey;
         if (hipEventRecord(w->ev1, s) != hipSuccess ||
             hipMemcpyAsync(w->h_state, w->st, sizeof(SolveState), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {

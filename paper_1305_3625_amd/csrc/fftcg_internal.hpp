@@ -15,6 +15,10 @@ namespace fftcg {
 // Device buffers of one in-flight solve (reused across solves of a plan).
 struct Workspace {
     int L = 0, M = 0, stride = 0;
+    // interval between FP64 checks seen in the last single solve on this
+    // workspace (first guess for the next one's chunk lengths; 0 = none)
+    int check_period = 0;
+    int check_period_prec = -1;  // precision and preconditioning it was seen with
     void* W = nullptr;  // pruned half spectrum, L x M/2 complex (FP64-sized)
     void* r = nullptr;  // working vectors, L*L doubles each (FP32 uses half)
     void* p = nullptr;
