@@ -11,7 +11,9 @@
 * padded L = 2048 (eps 1e-4, b ~ N(0,1)) in mixed precision: the error is
   certified from the oracle's FP64 residual of the GPU solution (a property
   that holds at any size), <= 1e-8;
-* edge cases: b = 0, maxit = 1, warm start at the solution, invalid d.
+* edge cases: b = 0, maxit = 1, warm start at the solution, invalid d;
+* results do not depend on how the host splits a solve into launched
+  chunks (bitwise, padded L = 512, both modes).
 """
 
 import numpy as np
@@ -138,6 +140,32 @@ def test_padded_L512(padded512, mode):
     print(f"mode {prec}: iters {info['iterations']} checks {info['checks']} err {err:.3e} "
           f"bound {info['error_bound']:.3e} ms {info['device_ms']:.2f}")
     assert err <= bar
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_results_independent_of_launch_chunking(padded512, mode):
+    """The host only chooses how many iterations each launched chunk holds,
+    from the check intervals seen so far in the solve and, in mixed
+    precision, in the previous solve on the same plan; every check and stop
+    decision is taken on the device, and every reduction has a fixed order.
+    So a solve gives bitwise the same x, iteration and check counts on a
+    fresh plan, after a solve of another instance, and after itself."""
+    prec, tol, _ = mode
+    inst, _ = padded512
+    other = c2_instance(1)
+    banner("chunking-independence", prec)
+    fresh = binding.Plan(512, 1, inst["ghat"])
+    x_a, info_a = _solve(fresh, inst, prec, tol)
+    used = binding.Plan(512, 1, inst["ghat"])
+    _, info_o = _solve(used, other, prec, tol)
+    x_b, info_b = _solve(used, inst, prec, tol)
+    x_c, info_c = _solve(used, inst, prec, tol)
+    print(f"mode {prec}: iters {info_a['iterations']} / other {info_o['iterations']} / "
+          f"{info_b['iterations']} / {info_c['iterations']}, checks {info_a['checks']}")
+    for x, info in ((x_b, info_b), (x_c, info_c)):
+        assert info["status"] == binding.OK
+        assert (info["iterations"], info["checks"]) == (info_a["iterations"], info_a["checks"])
+        assert np.array_equal(x, x_a)
 
 
 def test_padded_L2048_mixed_certified():
