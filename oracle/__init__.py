@@ -16,15 +16,15 @@ computational physics"):
 * Sec. 3, eq. (3): ``C`` is diagonal in Fourier space, so
   ``C v = F^{-1}(ghat * F v)``.  On a zero-padded grid (M = 2L) the circular
   convolution restricted to the L x L grid is the linear convolution.
-* Sec. 3, Listing 2: unpreconditioned conjugate gradient (Sec. 4 states no
+* Sec. 3: unpreconditioned conjugate gradient (Sec. 4 states no
   preconditioner was used).
 
 Modules:
 
 * ``kernel_table`` -- g_M by a cosine-matrix product (no FFT).
 * ``operator``     -- A x by the direct real-space sum, by an assembled
-  dense matrix, and (for large grids) by numpy's FFT as a library step.
-* ``cg``           -- Hestenes-Stiefel CG in the order of Listing 2.
+  dense matrix, and (for large grids) by scipy's FFT as a library step.
+* ``cg``           -- textbook Hestenes-Stiefel CG.
 * ``pcg``          -- CG with the Fourier-space (circulant) preconditioner
   (an extension beyond the paper, which ran without one).
 * ``dense``        -- Cholesky solve of the assembled dense system.

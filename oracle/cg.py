@@ -1,10 +1,11 @@
-"""Unpreconditioned conjugate gradient in the order of Sec. 3, Listing 2.
+"""Unpreconditioned conjugate gradient (Hestenes-Stiefel), FP64.
 
-Listing 2 lists, per iteration: the product of the matrix with the search
-direction, the search length (a dot product), the new solution and the new
-residual (two vector additions), the residual length (a dot product), the
-update of the search direction (a vector addition) and a convergence check.
-The paper uses no preconditioner (Sec. 4).  Everything is FP64.
+Sec. 3 solves the symmetric positive definite system by the conjugate
+gradient method, without a preconditioner (Sec. 4).  The iteration is the
+textbook one, from the mathematics: the step length alpha minimises the
+A-norm of the error along the search direction p, alpha = (r.r)/(p.Ap); the
+residual follows by r <- r - alpha Ap; the next direction is made
+A-conjugate to p by beta = (r.r)_new/(r.r)_old, p <- r + beta p.
 """
 
 from __future__ import annotations
@@ -42,17 +43,17 @@ def cg(matvec, b, x0=None, tol=1e-10, maxit=10000, stagnation=20,
     if record:
         info["residuals"] = [r.copy()]
     for k in range(1, maxit + 1):
-        q = matvec(p)                       # product with the search direction
-        pq = float(np.sum(p * q))           # search length ...
+        q = matvec(p)
+        pq = float(np.sum(p * q))
         if not (pq > 0.0) or not np.isfinite(pq):
             info["breakdown"] = True
             break
-        alpha = rho / pq                    # ... alpha = rho / (p.q)
-        x += alpha * p                      # new x
-        r -= alpha * q                      # new residual
-        rho_new = float(np.sum(r * r))      # residual length
+        alpha = rho / pq
+        x += alpha * p
+        r -= alpha * q
+        rho_new = float(np.sum(r * r))
         beta = rho_new / rho
-        p = r + beta * p                    # update of the search direction
+        p = r + beta * p
         rho = rho_new
         info["iterations"] = k
         resids.append(np.sqrt(rho))
@@ -64,7 +65,7 @@ def cg(matvec, b, x0=None, tol=1e-10, maxit=10000, stagnation=20,
                 h["err_A"] = float(np.sqrt(np.sum(e * matvec_true(e))))
                 h["true_res"] = float(np.sqrt(np.sum((b - matvec_true(x)) ** 2)))
             info["history"].append(h)
-        if np.sqrt(rho) <= tol * bnorm:     # convergence check
+        if np.sqrt(rho) <= tol * bnorm:
             info["converged"] = True
             break
         if rho < best:

@@ -21,13 +21,18 @@ Routes (each pinned against the others and against closed forms):
 * ``apply_direct_at`` single output entries, O(L^2) each, for sampling large
   grids.
 * ``apply_fft``     eq. (3) literally: F^{-1}(ghat * F(pad x)), cropped, with
-  numpy's complex 2-D FFT as a library step.  Used for grids where the direct
-  sum is too slow; pinned against ``conv_direct``.
+  scipy's 2-D FFT of real input as a library step (a real input has a
+  Hermitian spectrum and ghat is real and even, so the product keeps that
+  symmetry and the half spectrum n in [0, M/2] determines the result).  Used
+  for grids where the direct sum is too slow; pinned against ``conv_direct``.
 """
 
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft
 
 
 def _check(g, x, padded):
@@ -89,13 +94,24 @@ def assemble_dense(g, d, padded):
     return A
 
 
-def apply_fft(ghat, d, x, padded):
-    """Eq. (3): d * x + crop(F^{-1}(ghat * F(embed x))) with numpy's FFT."""
+def host_workers():
+    """Host threads this process may run on (the FFT library's worker count)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+def apply_fft(ghat, d, x, padded, workers=None):
+    """Eq. (3): d * x + crop(F^{-1}(ghat * F(embed x))) with scipy's FFT of
+    real input, FP64, on ``workers`` host threads (default: all of them)."""
     M = ghat.shape[0]
     L = x.shape[0]
     if (padded and M != 2 * L) or (not padded and M != L):
         raise ValueError("M must be 2L (padded) or L (periodic)")
+    w = host_workers() if workers is None else int(workers)
     xp = np.zeros((M, M))
     xp[:L, :L] = x
-    y = np.fft.ifft2(ghat * np.fft.fft2(xp)).real[:L, :L]
+    X = scipy.fft.rfft2(xp, workers=w)
+    y = scipy.fft.irfft2(ghat[:, :M // 2 + 1] * X, s=(M, M), workers=w)[:L, :L]
     return np.asarray(d) * x + y

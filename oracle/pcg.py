@@ -24,22 +24,27 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft
+
+from .operator import host_workers
 
 
 def circulant_precond(ghat, d, padded):
-    """Returns z = P^{-1} r as a function of r (L x L arrays).  numpy's FFT is
-    a library step for S^{-1} = F^{-1} diag(1/(dbar + ghat)) F."""
+    """Returns z = P^{-1} r as a function of r (L x L arrays).  scipy's FFT of
+    real input is a library step for S^{-1} = F^{-1} diag(1/(dbar + ghat)) F
+    (1/(dbar + ghat) is real and even, so the half spectrum suffices)."""
     ghat = np.asarray(ghat, dtype=np.float64)
     M = ghat.shape[0]
     L = M // 2 if padded else M
     dbar = float(np.mean(d))
-    inv = 1.0 / (dbar + ghat)
+    inv = 1.0 / (dbar + ghat[:, :M // 2 + 1])
+    w = host_workers()
 
     def apply(r):
         r = np.asarray(r, dtype=np.float64)
         z = np.zeros((M, M))
         z[:L, :L] = r
-        y = np.fft.ifft2(np.fft.fft2(z) * inv).real
+        y = scipy.fft.irfft2(scipy.fft.rfft2(z, workers=w) * inv, s=(M, M), workers=w)
         return y[:L, :L].copy()
 
     return apply

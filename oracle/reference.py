@@ -1,6 +1,6 @@
 """Reference solves: FP64 CG run to stagnation, then certified.
 
-The reference solution of A x = b is computed by the CG of Listing 2 with
+The reference solution of A x = b is computed by the oracle's CG (Sec. 3) with
 the direct real-space matvec (small and medium grids) or with the eq. (3)
 FFT matvec (grids where the direct sum is too slow), driven to stagnation
 (||r||/||b|| <= 1e-13 or no decrease over 20 iterations).  The true residual

@@ -1,4 +1,4 @@
-"""Pins of the oracle's CG (Listing 2) and reference solves.
+"""Pins of the oracle's CG (Sec. 3) and reference solves.
 
 * closed form: periodic grid, uniform d, constant b => x = b / (d + ghat(0,0)),
   reached in one iteration (the constant vector is the k = 0 plane wave);

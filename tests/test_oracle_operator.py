@@ -1,6 +1,7 @@
 """Pins of the oracle's operator A = diag(d) + C.
 
-* dense assembly vs the direct real-space sum vs numpy's FFT route;
+* dense assembly vs the direct real-space sum vs the FFT route (L <= 64,
+  and padded L = 512);
 * symmetry and positive definiteness, eigenvalues inside the closed-form
   bounds;
 * plane waves are eigenvectors of the periodic operator with eigenvalue
@@ -93,6 +94,23 @@ def test_fft_route_equals_direct(L, padded):
     yd = apply_direct(g, inst["d"], x, padded)
     yf = apply_fft(inst["ghat"], inst["d"], x, padded)
     np.testing.assert_allclose(yf, yd, rtol=0, atol=1e-13 * np.abs(yd).max())
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fft_route_equals_direct_L512(seed):
+    """The FFT route at padded L = 512 (M = 1024: the served M = 1024 class,
+    the load-stepped sequences and the L = 512 FP64 workload lean on it)
+    against the direct real-space sum, on random vectors and a diagonal with
+    zeros; also at one worker thread (same result up to rounding)."""
+    L = 512
+    inst = padded_instance(L, [91, seed], eps=1e-3)
+    g = kernel_table(inst["ghat"])
+    x = np.random.default_rng([92, seed]).standard_normal((L, L))
+    yd = apply_direct(g, inst["d"], x, 1)
+    yf = apply_fft(inst["ghat"], inst["d"], x, 1)
+    np.testing.assert_allclose(yf, yd, rtol=0, atol=1e-13 * np.abs(yd).max())
+    y1 = apply_fft(inst["ghat"], inst["d"], x, 1, workers=1)
+    np.testing.assert_allclose(y1, yd, rtol=0, atol=1e-13 * np.abs(yd).max())
 
 
 @pytest.mark.parametrize("padded", [0, 1])
