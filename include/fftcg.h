@@ -201,6 +201,20 @@ int fftcg_solve(fftcg_plan_t plan, int precision, const double* d,
 int fftcg_loadstep(fftcg_plan_t plan, const double* x, const double* t,
                    double* d, int* index, void* stream);
 
+/* fftcg_loadstep_noalloc -- fftcg_loadstep for callers that cannot allocate
+ * device or pinned memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): same arguments, rule and result, bitwise.
+ * Its argmax partials live in a 16 KiB array in the library's device memory
+ * (one per GPU, held until the process ends) instead of a workspace the plan
+ * allocates on first use; it calls no allocating routine.  That array holds
+ * the partials of at most 1024 blocks, which covers every plan's grid (the
+ * partial count is capped at 1024); FFTCG_EINVAL if a grid ever needed more.
+ * Every call on one GPU shares the array: calls that overlap on the same GPU
+ * (two host threads, or two streams) race and must be serialised by the
+ * caller.  index is a HOST pointer; blocks until the index is known.         */
+int fftcg_loadstep_noalloc(fftcg_plan_t plan, const double* x, const double* t,
+                           double* d, int* index, void* stream);
+
 /* fftcg_fracture -- the quasi-static fracture driver of Sec. 2: uniform
  * fibre stiffness k (> 0), displacement control, fibres breaking one at a
  * time.  Each step solves, at unit displacement, (I/k + G)_II f_I = 1_I on

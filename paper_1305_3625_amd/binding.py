@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD"
 # every symbol include/fftcg.h declares
 EXPORTS = [
     "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond", "fftcg_plan_info",
-    "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep", "fftcg_fracture",
+    "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_destroy",
     "fftcg_strerror", "fftcg_version", "fftcg_greens_spectrum",
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
         "fftcg_profile_apply": (I, [P, I, P, P, P, I, ctypes.POINTER(D), P]),
         "fftcg_solve": (I, [P, I, P, P, P, D, I, P, ctypes.POINTER(Info), P]),
         "fftcg_loadstep": (I, [P, P, P, P, ctypes.POINTER(I), P]),
+        "fftcg_loadstep_noalloc": (I, [P, P, P, P, ctypes.POINTER(I), P]),
         "fftcg_server_create": (I, [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]),
         "fftcg_submit": (I, [P, P, I, P, P, P, D, I, U64P]),
         "fftcg_submit_sequence": (I, [P, P, I, P, P, P, D, I, I, U64P]),
@@ -257,6 +258,15 @@ class Plan:
         st = load().fftcg_loadstep(self.h, _ptr(x), _ptr(t), _ptr(d), ctypes.byref(idx), _stream(stream))
         if st != OK:
             raise FftcgError(st, "fftcg_loadstep")
+        return idx.value
+
+    def loadstep_noalloc(self, x, t, d, stream=None):
+        """fftcg_loadstep with no allocation (the library's static scratch)."""
+        idx = ctypes.c_int(-2)
+        st = load().fftcg_loadstep_noalloc(self.h, _ptr(x), _ptr(t), _ptr(d), ctypes.byref(idx),
+                                           _stream(stream))
+        if st != OK:
+            raise FftcgError(st, "fftcg_loadstep_noalloc")
         return idx.value
 
 

@@ -3,6 +3,8 @@
 // to its threshold breaks).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "fftcg_dev.hpp"
 
@@ -106,6 +108,54 @@ void launch_breakstep(const double* x, const double* t, uint8_t* mask, int n, do
     const int nb = loadstep_blocks(n);
     hipLaunchKernelGGL(k_loadstep_partial<uint8_t>, dim3(nb), dim3(LS_NT), 0, s, x, t, mask, n, pv, pi);
     hipLaunchKernelGGL(k_loadstep_final<uint8_t>, dim3(1), dim3(LS_NT), 0, s, pv, pi, nb, n, mask, out, out_v);
+}
+
+// ---- load step without allocation ------------------------------------------
+// The argmax partials of one load step (at most LS_MAX_BLOCKS blocks: values,
+// then indices) and the result word, in a file-scope device array: every call
+// on a device shares that device's copy.  Nothing needs clearing: each call's
+// partial kernel writes every partial its final kernel reads, and the final
+// kernel writes the result word.  Calls that overlap on one device race on it.
+constexpr int LS_MAX_BLOCKS = 1024;
+constexpr size_t LS_SCRATCH_BYTES = 16384;
+static_assert(LS_MAX_BLOCKS * (sizeof(double) + sizeof(int)) + 4 * sizeof(int) <= LS_SCRATCH_BYTES,
+              "load-step scratch too small");
+static __device__ __align__(256) unsigned char scratch[LS_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of this device's copy of `scratch` (looked up once per
+// device, with that device current); nullptr on a HIP error.
+static void* scratch_on(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+int loadstep_noalloc(const double* x, const double* t, double* d, int n, int* index, hipStream_t s) {
+    const int nb = loadstep_blocks(n);
+    if (n < 1 || nb > LS_MAX_BLOCKS) return -1;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -2;
+    unsigned char* base = (unsigned char*)scratch_on(dev);
+    if (!base) return -2;
+    double* pv = (double*)base;
+    int* pi = (int*)(base + LS_MAX_BLOCKS * sizeof(double));
+    int* out = pi + LS_MAX_BLOCKS;
+    launch_loadstep(x, t, d, n, pv, pi, out, s);
+    if (hipGetLastError() != hipSuccess) return -2;
+    int h = -1;
+    if (hipMemcpyAsync(&h, out, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return -2;
+    *index = h;
+    return 0;
 }
 
 __global__ void k_fill(double* __restrict__ a, double v, int n) {

@@ -14,6 +14,11 @@ void launch_loadstep(const double* x, const double* t, double* d, int n, double*
 // the same over mask != 0, mask[i*] = 0, and *out_v = x[i*] / t[i*].
 void launch_breakstep(const double* x, const double* t, uint8_t* mask, int n, double* pv, int* pi, int* out,
                       double* out_v, hipStream_t s);
+// launch_loadstep with its partials in the library's static device array
+// (no allocation), then *index (host) = i*.  Blocks.  0 on success, -1 if n
+// is outside [1, 2^31) or needs more partials than the array holds, -2 on a
+// HIP error.
+int loadstep_noalloc(const double* x, const double* t, double* d, int n, int* index, hipStream_t s);
 // a[i] = v, i < n.
 void launch_fill(double* a, double v, int n, hipStream_t s);
 

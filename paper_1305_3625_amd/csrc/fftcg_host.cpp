@@ -689,6 +689,15 @@ extern "C" int fftcg_loadstep(fftcg_plan_t plan, const double* x, const double* 
     return rc;
 }
 
+extern "C" int fftcg_loadstep_noalloc(fftcg_plan_t plan, const double* x, const double* t, double* d, int* index,
+                                      void* stream) {
+    if (!plan || !x || !t || !d || !index) return FFTCG_EINVAL;
+    const long n = (long)plan->L * plan->L;
+    if (n > 0x7fffffffL) return FFTCG_EINVAL;
+    const int rc = loadstep_noalloc(x, t, d, (int)n, index, (hipStream_t)stream);
+    return rc == 0 ? FFTCG_OK : (rc == -1 ? FFTCG_EINVAL : FFTCG_EDEVICE);
+}
+
 // ---- misc -------------------------------------------------------------------
 extern "C" const char* fftcg_strerror(int status) {
     switch (status) {
