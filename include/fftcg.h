@@ -50,7 +50,7 @@ extern "C" {
 #define FFTCG_EAGAIN     -6   /* server queue full; retry later             */
 #define FFTCG_EDEVICE    -7   /* HIP runtime error / no usable gfx950 GPU   */
 #define FFTCG_ENOTFOUND  -8   /* unknown or already retired ticket          */
-#define FFTCG_ECANCELED  -9   /* request cancelled by server destruction    */
+#define FFTCG_ECANCELED  -9   /* request cancelled by server shutdown       */
 
 /* ---- precision modes ----------------------------------------------------
  * FFTCG_FP64 : every step in FP64.
@@ -147,6 +147,17 @@ int fftcg_plan_set_engine(fftcg_plan_t plan, int engine);
  * Not to be called concurrently with solves on the same plan.             */
 int fftcg_plan_set_precond(fftcg_plan_t plan, int kind);
 
+/* fftcg_plan_set_error_target -- the certified relative-error target tau of
+ * later solves in `precision` on this plan (fftcg_solve, fftcg_fracture, and
+ * server requests admitted afterwards).  tau = 0 (the default) makes tau
+ * equal to each solve's residual tolerance tol; 0 < tau < 1 fixes it, e.g.
+ * 1e-10 for FFTCG_FP64 and 1e-8 for FFTCG_MIXED, whatever tol is.  A solve
+ * then stops when ||r||/||b|| <= tol AND the residual certifies
+ * ||x - x*||/||x*|| <= tau (see fftcg_solve).  FFTCG_EINVAL for another
+ * precision or tau, or while server requests use the plan.  Not to be called
+ * concurrently with solves on the same plan.                               */
+int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, double tau);
+
 /* Reports L, M, padded, and the plan's device bytes (any pointer may be NULL). */
 int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* device_bytes);
 
@@ -184,8 +195,13 @@ int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d,
  *   stream     hipStream_t used for all work; the call blocks until done.
  * Stopping: the residual rule AND the certified rule
  *   ||r|| <= tau * lambda_lb * ||x|| / (1 + tau),  lambda_lb = min d + min ghat,
- * with tau = tol, which guarantees ||x - x*||/||x*|| <= tol (both checked on
- * an FP64 true residual).  b = 0 gives x = 0, FFTCG_OK and 0 iterations.    */
+ * which guarantees ||x - x*||/||x*|| <= tau (both checked on an FP64 true
+ * residual).  tau = tol unless the plan fixes it per precision
+ * (fftcg_plan_set_error_target).  b = 0 gives x = 0, FFTCG_OK and 0
+ * iterations.  A non-finite value met inside CG (for instance from a
+ * non-finite x0) ends the solve with FFTCG_EBREAKDOWN.  x is the solve's
+ * working iterate: after an error other than FFTCG_EINVAL its contents are
+ * unspecified.                                                            */
 int fftcg_solve(fftcg_plan_t plan, int precision, const double* d,
                 const double* b, const double* x0, double tol, int maxit,
                 double* x, fftcg_info* info, void* stream);
@@ -304,7 +320,17 @@ int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap, int* n);
 /* Counters of the server (host pointer).                                   */
 int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out);
 
-/* Stops the server; requests still queued or in flight end FFTCG_ECANCELED. */
+/* fftcg_server_shutdown -- stops the scheduler; every request still queued
+ * or in flight ends with FFTCG_ECANCELED (info.iterations: the iterations it
+ * had run), except one whose results were already being copied back, which
+ * keeps its own status.  Device memory of the slots is released.  Results
+ * stay pollable until fftcg_server_destroy; later submissions return
+ * FFTCG_ECANCELED.  A second call does nothing.  Blocks until the device
+ * work of the server's streams has finished.                               */
+int fftcg_server_shutdown(fftcg_server_t srv);
+
+/* Shuts the server down (fftcg_server_shutdown) and frees it with every
+ * unpolled result; the handle is invalid afterwards.                       */
 int fftcg_server_destroy(fftcg_server_t srv);
 
 /* Static description of a status code.                                     */

@@ -28,10 +28,12 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD"
 
 # every symbol include/fftcg.h declares
 EXPORTS = [
-    "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond", "fftcg_plan_info",
+    "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond",
+    "fftcg_plan_set_error_target", "fftcg_plan_info",
     "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
-    "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_destroy",
+    "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_shutdown",
+    "fftcg_server_destroy",
     "fftcg_strerror", "fftcg_version", "fftcg_greens_spectrum",
 ]
 
@@ -95,6 +97,7 @@ def load(path: str = LIB_PATH):
         "fftcg_plan_destroy": (I, [P]),
         "fftcg_plan_set_engine": (I, [P, I]),
         "fftcg_plan_set_precond": (I, [P, I]),
+        "fftcg_plan_set_error_target": (I, [P, I, D]),
         "fftcg_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                 ctypes.POINTER(S)]),
         "fftcg_apply": (I, [P, I, P, P, P, P]),
@@ -109,6 +112,7 @@ def load(path: str = LIB_PATH):
         "fftcg_poll_sequence": (I, [P, ctypes.c_uint64, P, P, P, ctypes.POINTER(Info)]),
         "fftcg_server_completed": (I, [P, ctypes.POINTER(ctypes.c_uint64), I, ctypes.POINTER(I)]),
         "fftcg_server_get_stats": (I, [P, ctypes.POINTER(ServerStats)]),
+        "fftcg_server_shutdown": (I, [P]),
         "fftcg_server_destroy": (I, [P]),
         "fftcg_fracture": (I, [P, I, ctypes.c_double, P, I, ctypes.c_double, I, P, P, P, P, P]),
         "fftcg_strerror": (ctypes.c_char_p, [I]),
@@ -192,6 +196,12 @@ class Plan:
         st = load().fftcg_plan_set_precond(self.h, kind)
         if st != OK:
             raise FftcgError(st, "fftcg_plan_set_precond")
+
+    def set_error_target(self, precision: int, tau: float):
+        """Fixes the certified error target of `precision` (0: follow tol)."""
+        st = load().fftcg_plan_set_error_target(self.h, int(precision), float(tau))
+        if st != OK:
+            raise FftcgError(st, "fftcg_plan_set_error_target")
 
     def info(self):
         L, M, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -345,6 +355,12 @@ class Server:
         if st != OK:
             raise FftcgError(st, "fftcg_server_get_stats")
         return s.as_dict()
+
+    def shutdown(self):
+        """Stops the server: unfinished requests end ECANCELED, results stay pollable."""
+        st = load().fftcg_server_shutdown(self.h)
+        if st != OK:
+            raise FftcgError(st, "fftcg_server_shutdown")
 
     def close(self):
         if getattr(self, "h", None) is not None:

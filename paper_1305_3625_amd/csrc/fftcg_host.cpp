@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -240,7 +241,7 @@ int fftcg::plan_validate(int L, int padded, const double* g, double* gmin_out, d
     return FFTCG_OK;
 }
 
-extern "C" int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftcg_plan_t* out) {
+extern "C" int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftcg_plan_t* out) try {
     if (!out) return FFTCG_EINVAL;
     double gmin = 0, gmax = 0;
     int rc = plan_validate(L, padded, kernel_spectrum, &gmin, &gmax);
@@ -248,7 +249,9 @@ extern "C" int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftc
     rc = check_device();
     if (rc != FFTCG_OK) return rc;
     const int M = padded ? 2 * L : L;
-    fftcg_plan_s* p = new (std::nothrow) fftcg_plan_s();
+    // owned here until returned, so an exception below releases it
+    std::unique_ptr<fftcg_plan_s> owner(new (std::nothrow) fftcg_plan_s());
+    fftcg_plan_s* p = owner.get();
     if (!p) return FFTCG_ENOMEM;
     p->L = L;
     p->M = M;
@@ -289,24 +292,21 @@ extern "C" int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftc
             r2 = FFTCG_EDEVICE;
     }
     if (r2 == FFTCG_OK) r2 = fused_init(p, kernel_spectrum);
-    if (r2 != FFTCG_OK) {
-        delete p;
-        return r2 == FFTCG_EDEVICE ? FFTCG_EDEVICE : FFTCG_ENOMEM;
-    }
+    if (r2 != FFTCG_OK) return r2 == FFTCG_EDEVICE ? FFTCG_EDEVICE : FFTCG_ENOMEM;
     p->tabs = PlanTabs{p->tw32, p->ghq32, p->ghN32, p->tw64, p->ghq64, p->ghN64};
     p->device_bytes = bytes + p->fused_bytes;
     p->engine = FFTCG_ENGINE_AUTO;
-    *out = p;
+    *out = owner.release();
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
-extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) {
+extern "C" int fftcg_plan_destroy(fftcg_plan_t plan) try {
     if (!plan) return FFTCG_EINVAL;
     if (plan->refs.load() > 0) return FFTCG_EINVAL;
     (void)hipDeviceSynchronize();
     delete plan;
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
 // AUTO: one workgroup per solve beats four kernel launches per iteration on
 // the smallest grids.  A single solve takes the fused engine up to M = 64; a
@@ -328,7 +328,7 @@ int fftcg::server_engine(const fftcg_plan_s* p) {
     return p->engine;
 }
 
-extern "C" int fftcg_plan_set_engine(fftcg_plan_t plan, int engine) {
+extern "C" int fftcg_plan_set_engine(fftcg_plan_t plan, int engine) try {
     if (!plan) return FFTCG_EINVAL;
     if (engine == FFTCG_ENGINE_AUTO) {
         plan->engine = engine;
@@ -345,9 +345,9 @@ extern "C" int fftcg_plan_set_engine(fftcg_plan_t plan, int engine) {
         return FFTCG_OK;
     }
     return FFTCG_EINVAL;
-}
+} FFTCG_ABI_CATCH
 
-extern "C" int fftcg_plan_set_precond(fftcg_plan_t plan, int kind) {
+extern "C" int fftcg_plan_set_precond(fftcg_plan_t plan, int kind) try {
     if (!plan) return FFTCG_EINVAL;
     if (kind != FFTCG_PRECOND_NONE && kind != FFTCG_PRECOND_CIRCULANT) return FFTCG_EINVAL;
     if (kind == FFTCG_PRECOND_CIRCULANT && !plan->ops) return FFTCG_EINVAL;
@@ -355,16 +355,26 @@ extern "C" int fftcg_plan_set_precond(fftcg_plan_t plan, int kind) {
     std::lock_guard<std::mutex> lk(plan->mu);
     plan->precond = kind;
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
-extern "C" int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* device_bytes) {
+extern "C" int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, double tau) try {
+    if (!plan) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    if (!(tau == 0.0 || (tau > 0.0 && tau < 1.0))) return FFTCG_EINVAL;
+    if (plan->refs.load() > 0) return FFTCG_EINVAL;  // requests in a server use it
+    std::lock_guard<std::mutex> lk(plan->mu);
+    plan->tau_fixed[precision == FFTCG_MIXED ? 1 : 0] = tau;
+    return FFTCG_OK;
+} FFTCG_ABI_CATCH
+
+extern "C" int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* device_bytes) try {
     if (!plan) return FFTCG_EINVAL;
     if (L) *L = plan->L;
     if (M) *M = plan->M;
     if (padded) *padded = plan->pad;
     if (device_bytes) *device_bytes = plan->device_bytes;
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
 // ---- apply -------------------------------------------------------------------
 static bool overlap(const void* a, const void* b, size_t n) {
@@ -374,7 +384,7 @@ static bool overlap(const void* a, const void* b, size_t n) {
 }
 
 extern "C" int fftcg_apply(fftcg_plan_t plan, int precision, const double* d, const double* x, double* y,
-                           void* stream) {
+                           void* stream) try {
     if (!plan || !d || !x || !y) return FFTCG_EINVAL;
     if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
     const size_t nb = (size_t)plan->L * plan->L * 8;
@@ -390,10 +400,10 @@ extern "C" int fftcg_apply(fftcg_plan_t plan, int precision, const double* d, co
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(plan->apply_ev, s));
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
 extern "C" int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d, const double* x, double* y,
-                                   int reps, double* ms_per_pass, void* stream) {
+                                   int reps, double* ms_per_pass, void* stream) try {
     if (!plan || !d || !x || !y || !ms_per_pass || reps < 1) return FFTCG_EINVAL;
     if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
     const size_t nb = (size_t)plan->L * plan->L * 8;
@@ -431,7 +441,7 @@ extern "C" int fftcg_profile_apply(fftcg_plan_t plan, int precision, const doubl
     if (rc == FFTCG_OK)
         for (int pass = 0; pass < 3; ++pass) ms_per_pass[pass] = acc[pass] / (blocks * RUN);
     return rc;
-}
+} FFTCG_ABI_CATCH
 
 // ---- solve -------------------------------------------------------------------
 Workspace* fftcg::plan_acquire(fftcg_plan_s* p) {
@@ -459,7 +469,10 @@ void fftcg::plan_release(fftcg_plan_s* p, Workspace* w) {
 void fftcg::init_state(SolveState* h, const fftcg_plan_s* p, int precision, double tol, int maxit, int refresh) {
     memset(h, 0, sizeof(SolveState));
     h->tol = tol;
-    h->tau = tol;  // certified relative error target = the residual tolerance
+    // certified relative error target: the plan's fixed one for this
+    // precision, else the residual tolerance
+    h->tau = p->tau_fixed[precision == FFTCG_MIXED ? 1 : 0] > 0.0 ? p->tau_fixed[precision == FFTCG_MIXED ? 1 : 0]
+                                                                   : tol;
     h->gmin = p->gmin;
     h->maxit = maxit;
     h->refresh = precision == FFTCG_MIXED ? refresh : 0;
@@ -660,18 +673,18 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
 }
 
 extern "C" int fftcg_solve(fftcg_plan_t plan, int precision, const double* d, const double* b, const double* x0,
-                           double tol, int maxit, double* x, fftcg_info* info, void* stream) {
+                           double tol, int maxit, double* x, fftcg_info* info, void* stream) try {
     int rc = solve_validate(plan, precision, d, b, tol, maxit, x);
     if (rc != FFTCG_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (plan_engine(plan) == FFTCG_ENGINE_FUSED) return fused_solve(plan, precision, d, b, x0, tol, maxit, x, info, s);
     if (!plan->ops) return FFTCG_EINVAL;
     return solve_multipass(plan, precision, d, b, x0, tol, maxit, x, info, s);
-}
+} FFTCG_ABI_CATCH
 
 // ---- load step ---------------------------------------------------------------
 extern "C" int fftcg_loadstep(fftcg_plan_t plan, const double* x, const double* t, double* d, int* index,
-                              void* stream) {
+                              void* stream) try {
     if (!plan || !x || !t || !d || !index) return FFTCG_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     Workspace* w = plan_acquire(plan);
@@ -687,16 +700,16 @@ extern "C" int fftcg_loadstep(fftcg_plan_t plan, const double* x, const double* 
         *index = w->h_ls[0];
     plan_release(plan, w);
     return rc;
-}
+} FFTCG_ABI_CATCH
 
 extern "C" int fftcg_loadstep_noalloc(fftcg_plan_t plan, const double* x, const double* t, double* d, int* index,
-                                      void* stream) {
+                                      void* stream) try {
     if (!plan || !x || !t || !d || !index) return FFTCG_EINVAL;
     const long n = (long)plan->L * plan->L;
     if (n > 0x7fffffffL) return FFTCG_EINVAL;
     const int rc = loadstep_noalloc(x, t, d, (int)n, index, (hipStream_t)stream);
     return rc == 0 ? FFTCG_OK : (rc == -1 ? FFTCG_EINVAL : FFTCG_EDEVICE);
-}
+} FFTCG_ABI_CATCH
 
 // ---- misc -------------------------------------------------------------------
 extern "C" const char* fftcg_strerror(int status) {
@@ -726,7 +739,7 @@ extern "C" const char* fftcg_version(void) { return "fftcg 0.1.0 (gfx950)"; }
 // breaks next, at the displacement D = t_i/f_i; then the next step solves
 // again, warm-started from the previous forces.
 extern "C" int fftcg_fracture(fftcg_plan_t plan, int precision, double k, const double* t, int steps, double tol,
-                              int maxit, double* f, int* broken, double* dbreak, int* iters, void* stream) {
+                              int maxit, double* f, int* broken, double* dbreak, int* iters, void* stream) try {
     if (!plan || !t || !f || !broken || !dbreak) return FFTCG_EINVAL;
     if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
     if (!(k > 0.0) || !isfinite(k) || !(tol > 0.0 && tol < 1.0) || maxit < 1) return FFTCG_EINVAL;
@@ -777,4 +790,4 @@ extern "C" int fftcg_fracture(fftcg_plan_t plan, int precision, double k, const 
     if (h_v) (void)hipHostFree(h_v);
     if (h_i) (void)hipHostFree(h_i);
     return rc;
-}
+} FFTCG_ABI_CATCH

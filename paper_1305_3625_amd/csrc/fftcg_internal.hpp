@@ -4,11 +4,25 @@
 
 #include <atomic>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "engine.hpp"
 #include "fftcg.h"
 #include "fftcg_types.hpp"
+
+// Catch clauses of every C entry point, written as a function-try-block
+// (`extern "C" int f(...) try { ... } FFTCG_ABI_CATCH`): no C++ exception
+// crosses the C ABI.  A failed allocation of host containers becomes
+// FFTCG_ENOMEM; anything else the C++ runtime throws (thread or mutex
+// errors) FFTCG_EDEVICE.
+#define FFTCG_ABI_CATCH                  \
+    catch (const std::bad_alloc&) {      \
+        return FFTCG_ENOMEM;             \
+    }                                    \
+    catch (...) {                        \
+        return FFTCG_EDEVICE;            \
+    }
 
 namespace fftcg {
 
@@ -63,6 +77,9 @@ struct fftcg_plan_s {
     int L = 0, M = 0, pad = 0, device = 0;
     int engine = FFTCG_ENGINE_AUTO;
     int precond = FFTCG_PRECOND_NONE;
+    // certified error target per precision (FFTCG_FP64, FFTCG_MIXED); 0: the
+    // solve's residual tolerance
+    double tau_fixed[2] = {0.0, 0.0};
     int stride = 64;
     double gmin = 0, gmax = 0;
     const fftcg::EngineOps* ops = nullptr;

@@ -81,7 +81,7 @@ void dft_lines(double* a, int M, size_t ls, size_t os, const std::vector<std::co
 
 }  // namespace
 
-extern "C" int fftcg_greens_spectrum(int L, int padded, double nu, double E, double a, double* spectrum) {
+extern "C" int fftcg_greens_spectrum(int L, int padded, double nu, double E, double a, double* spectrum) try {
     if (!spectrum || (padded != 0 && padded != 1)) return FFTCG_EINVAL;
     if (L < 2 || (L & (L - 1)) || (padded ? 2 * L : L) > 8192) return FFTCG_EINVAL;
     if (!(E > 0.0) || !(a > 0.0) || !isfinite(E) || !isfinite(a) || !isfinite(nu) || !(fabs(nu) < 1.0))
@@ -117,4 +117,4 @@ extern "C" int fftcg_greens_spectrum(int L, int padded, double nu, double E, dou
                 spectrum[(size_t)m2 * M + n2] = v;
         }
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH

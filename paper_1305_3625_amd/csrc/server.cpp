@@ -100,6 +100,7 @@ struct Class {
     int inflight = 0;  // chunks launched and not yet seen complete
     int next_ev = 0;
     size_t footprint = 0;  // device bytes per slot
+    int refresh = 50;      // MIXED: iterations between FP64 checks
 };
 
 }  // namespace
@@ -110,6 +111,7 @@ struct fftcg_server_s {
     std::condition_variable cv;
     std::thread thread;
     std::atomic<bool> stop{false};
+    bool shut = false;  // fftcg_server_shutdown has begun (guarded by mu)
     std::map<std::pair<fftcg_plan_s*, int>, std::unique_ptr<Class>> classes;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
     uint64_t next_ticket = 1;
@@ -216,6 +218,7 @@ int make_class(fftcg_server_s* srv, fftcg_plan_s* plan, int precision, Class** o
     c->plan = plan;
     c->precision = precision;
     c->footprint = slot_footprint(plan);
+    c->refresh = srv->opts.refresh_period;
     const int ms = srv->opts.max_slots;
     bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
               hipMalloc((void**)&c->d_table, sizeof(SlotDesc) * ms) == hipSuccess &&
@@ -255,7 +258,7 @@ void start_solve(Class* c, int idx) {
     Slot* s = c->slots[idx].get();
     Request* q = s->req;
     s->gen += 1;
-    init_state(s->pin_state, c->plan, q->precision, q->tol, q->maxit, 50);
+    init_state(s->pin_state, c->plan, q->precision, q->tol, q->maxit, c->refresh);
     s->pin_state->gen = s->gen;
     (void)hipMemcpyAsync(s->ws->st, s->pin_state, sizeof(SolveState), hipMemcpyHostToDevice, c->stream);
     if (q->precision == FFTCG_MIXED) {
@@ -457,7 +460,15 @@ void scheduler(fftcg_server_s* srv) {
             for (auto& kv : srv->classes) cls.push_back(kv.second.get());
         }
         bool busy = false;
-        for (Class* c : cls) busy |= progress(srv, c);
+        for (Class* c : cls) {
+            // an exception (a failed host allocation) must not end the
+            // thread: the class is simply visited again on the next pass
+            try {
+                busy |= progress(srv, c);
+            } catch (...) {
+                busy = true;
+            }
+        }
         if (!busy) {
             std::unique_lock<std::mutex> lk(srv->mu);
             if (srv->queued == 0 && !srv->stop.load()) srv->cv.wait_for(lk, std::chrono::milliseconds(2));
@@ -536,7 +547,7 @@ void free_request_buffers(fftcg_server_s* srv, Request* q) {
 
 }  // namespace
 
-extern "C" int fftcg_server_create(const fftcg_server_opts* opts, fftcg_server_t* out) {
+extern "C" int fftcg_server_create(const fftcg_server_opts* opts, fftcg_server_t* out) try {
     if (!opts || !out) return FFTCG_EINVAL;
     if (opts->memory_budget == 0 || opts->max_slots < 0 || opts->chunk_iters < 0 || opts->refresh_period < 0 ||
         opts->queue_cap < 0)
@@ -554,7 +565,7 @@ extern "C" int fftcg_server_create(const fftcg_server_opts* opts, fftcg_server_t
     s->thread = std::thread(scheduler, s);
     *out = s;
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
 static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, const double* d, const double* b,
                          const double* x0, const double* t, double tol, int maxit, int steps, uint64_t* ticket) {
@@ -572,6 +583,7 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
             if (!(t[i] > 0.0) || !isfinite(t[i])) return FFTCG_EINVAL;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->shut) return FFTCG_ECANCELED;
         if (srv->queued >= srv->opts.queue_cap) return FFTCG_EAGAIN;
     }
     std::unique_ptr<Request> q(new (std::nothrow) Request());
@@ -596,9 +608,9 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     if (x0) memcpy(q->pin_in + 2 * n, x0, n * 8);
     if (t) memcpy(q->pin_in + (x0 ? 3 : 2) * n, t, n * 8);
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->queued >= srv->opts.queue_cap) {
+    if (srv->shut || srv->queued >= srv->opts.queue_cap) {
         free_request_buffers(srv, q.get());
-        return FFTCG_EAGAIN;
+        return srv->shut ? FFTCG_ECANCELED : FFTCG_EAGAIN;
     }
     Class* c = nullptr;
     auto it = srv->classes.find({plan, precision});
@@ -611,28 +623,40 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     } else {
         c = it->second.get();
     }
-    q->ticket = srv->next_ticket++;
-    *ticket = q->ticket;
+    // the two container insertions may throw (std::bad_alloc): the request
+    // is queued only once the ticket map owns it, and leaves the map again
+    // if queueing fails, so no container is left pointing at a freed request
+    const uint64_t tk = srv->next_ticket;
+    Request* raw = q.get();
+    raw->ticket = tk;
+    srv->requests.emplace(tk, std::move(q));
+    try {
+        c->pending.push_back(raw);
+    } catch (...) {
+        free_request_buffers(srv, raw);
+        srv->requests.erase(tk);
+        throw;
+    }
+    srv->next_ticket += 1;
+    *ticket = tk;
     plan->refs.fetch_add(1);
-    c->pending.push_back(q.get());
     srv->queued += 1;
     srv->stats.submitted += 1;
-    srv->requests[q->ticket] = std::move(q);
     srv->cv.notify_all();
     return FFTCG_OK;
 }
 
 extern "C" int fftcg_submit(fftcg_server_t srv, fftcg_plan_t plan, int precision, const double* d, const double* b,
-                            const double* x0, double tol, int maxit, uint64_t* ticket) {
+                            const double* x0, double tol, int maxit, uint64_t* ticket) try {
     return submit_common(srv, plan, precision, d, b, x0, nullptr, tol, maxit, 0, ticket);
-}
+} FFTCG_ABI_CATCH
 
 extern "C" int fftcg_submit_sequence(fftcg_server_t srv, fftcg_plan_t plan, int precision, const double* d,
                                      const double* b, const double* t, double tol, int maxit, int steps,
-                                     uint64_t* ticket) {
+                                     uint64_t* ticket) try {
     if (!t || steps < 1 || steps > kMaxSteps) return FFTCG_EINVAL;
     return submit_common(srv, plan, precision, d, b, nullptr, t, tol, maxit, steps, ticket);
-}
+} FFTCG_ABI_CATCH
 
 static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
                        fftcg_info* info, bool seq) {
@@ -659,16 +683,16 @@ static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* brok
     return st;
 }
 
-extern "C" int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info) {
+extern "C" int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info) try {
     return poll_common(srv, ticket, x, nullptr, nullptr, info, false);
-}
+} FFTCG_ABI_CATCH
 
 extern "C" int fftcg_poll_sequence(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
-                                   fftcg_info* info) {
+                                   fftcg_info* info) try {
     return poll_common(srv, ticket, x, broken, step_iters, info, true);
-}
+} FFTCG_ABI_CATCH
 
-extern "C" int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap, int* n) {
+extern "C" int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap, int* n) try {
     if (!srv || !n || cap < 0 || (cap > 0 && !out)) return FFTCG_EINVAL;
     std::lock_guard<std::mutex> lk(srv->mu);
     int k = 0;
@@ -678,9 +702,9 @@ extern "C" int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap
     }
     *n = k;
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
-extern "C" int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out) {
+extern "C" int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out) try {
     if (!srv || !out) return FFTCG_EINVAL;
     std::lock_guard<std::mutex> lk(srv->mu);
     *out = srv->stats;
@@ -688,14 +712,71 @@ extern "C" int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* ou
     out->queued = srv->queued;
     out->in_flight = srv->in_flight.load();
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH
 
-extern "C" int fftcg_server_destroy(fftcg_server_t srv) {
-    if (!srv) return FFTCG_EINVAL;
+// Stops the scheduler, then ends every request still queued or running with
+// FFTCG_ECANCELED (a solve whose results were already being copied back
+// finishes with its own status) and releases the device memory.  Results stay
+// pollable.  Runs once; later calls return at once.
+static void shutdown_server(fftcg_server_s* srv) {
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->shut) return;
+        srv->shut = true;  // later submissions return FFTCG_ECANCELED
+    }
     srv->stop.store(true);
     srv->cv.notify_all();
     if (srv->thread.joinable()) srv->thread.join();
+    // the scheduler has stopped and no submission adds a class any more: the
+    // classes are this thread's alone
+    for (auto& kv : srv->classes) {
+        Class* c = kv.second.get();
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        for (auto& sp : c->slots) {
+            Slot* s = sp.get();
+            Request* q = s->req;
+            if (!q) continue;
+            if (!s->retiring) {
+                // the iterations done so far go into the canceled request's info
+                if (hipMemcpy(s->pin_state, s->ws->st, sizeof(SolveState), hipMemcpyDeviceToHost) != hipSuccess)
+                    memset(s->pin_state, 0, sizeof(SolveState));
+            }
+            const SolveState st = *s->pin_state;
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (s->retiring) {
+                // its result copies have landed (the stream is synchronised)
+                if (q->steps > 0) q->step_iters.push_back(st.iters);
+                finish_request(srv, q, q->x_nomem ? FFTCG_ENOMEM : st.status, st);
+            } else {
+                finish_request(srv, q, FFTCG_ECANCELED, st);
+            }
+            s->req = nullptr;
+            s->retiring = false;
+            srv->in_flight.fetch_sub(1);
+        }
+        std::lock_guard<std::mutex> lk(srv->mu);
+        const SolveState none{};
+        for (Request* q : c->pending) {
+            finish_request(srv, q, FFTCG_ECANCELED, none);
+            srv->queued -= 1;
+        }
+        c->pending.clear();
+    }
     for (auto& kv : srv->classes) destroy_class(kv.second.get());
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->classes.clear();
+    srv->bytes_in_use.store(0);
+}
+
+extern "C" int fftcg_server_shutdown(fftcg_server_t srv) try {
+    if (!srv) return FFTCG_EINVAL;
+    shutdown_server(srv);
+    return FFTCG_OK;
+} FFTCG_ABI_CATCH
+
+extern "C" int fftcg_server_destroy(fftcg_server_t srv) try {
+    if (!srv) return FFTCG_EINVAL;
+    shutdown_server(srv);
     for (auto& kv : srv->requests) {
         Request* q = kv.second.get();
         if (!q->done) q->plan->refs.fetch_sub(1);
@@ -704,4 +785,4 @@ extern "C" int fftcg_server_destroy(fftcg_server_t srv) {
     for (auto& kv : srv->pin_free) (void)hipHostFree(kv.second);
     delete srv;
     return FFTCG_OK;
-}
+} FFTCG_ABI_CATCH

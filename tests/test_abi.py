@@ -120,3 +120,37 @@ def test_server_create_without_gpu(lib):
     o = binding.ServerOpts(1 << 30, 0, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     assert lib.fftcg_server_create(ctypes.byref(o), ctypes.byref(h)) == binding.EDEVICE
+
+
+def test_new_calls_reject_null(lib):
+    P = ctypes.c_void_p
+    idx = ctypes.c_int()
+    assert lib.fftcg_loadstep_noalloc(None, P(1), P(2), P(3), ctypes.byref(idx), None) == binding.EINVAL
+    assert lib.fftcg_plan_set_error_target(None, 0, 1e-10) == binding.EINVAL
+    assert lib.fftcg_server_shutdown(None) == binding.EINVAL
+
+
+CSRC = os.path.join(ROOT, "paper_1305_3625_amd", "csrc")
+
+
+def test_every_entry_point_catches_exceptions():
+    """Nothing throws across the C ABI: every int-returning entry point is a
+    function-try-block whose handlers map exceptions to status codes."""
+    found = []
+    for name in sorted(os.listdir(CSRC)):
+        if not name.endswith((".cpp", ".hip")):
+            continue
+        src = open(os.path.join(CSRC, name)).read()
+        for m in re.finditer(r'extern "C" int (fftcg_\w+)\([^{;]*\)\s*(try)?\s*\{', src):
+            found.append(m.group(1))
+            assert m.group(2) == "try", f"{name}: {m.group(1)} is not guarded"
+            # the body's closing brace is followed by the handlers
+            depth, i = 0, m.end() - 1
+            while True:
+                depth += {"{": 1, "}": -1}.get(src[i], 0)
+                if depth == 0:
+                    break
+                i += 1
+            assert src[i + 1:i + 40].lstrip().startswith("FFTCG_ABI_CATCH"), m.group(1)
+    declared = [s for s in header_symbols() if s not in ("fftcg_strerror", "fftcg_version")]
+    assert sorted(found) == sorted(declared)

@@ -233,3 +233,74 @@ def test_loadstep_sequence_replay():
     # the returned x is the last step's solution (before its own break)
     assert relerr(x_gpu, x_ref) <= 1e-8
     srv.close()
+
+
+@pytest.mark.parametrize("M", [128, 512])   # a fused class and a multi-pass class
+def test_refresh_period_option(plans, M):
+    """The server's refresh_period sets the mixed solves' FP64 check period:
+    a short period adds checks, and the results stay within 1e-8 of the
+    oracle either way."""
+    banner("serve-refresh-period", M)
+    r = c4_request(600 + M, M)
+    xr, _ = reference_solve(spectrum(M, EPS), r["d"], r["b"], 1, route="fft")
+    checks = {}
+    for period in (0, 4):
+        srv = binding.Server(memory_budget=1 << 30, refresh_period=period)
+        st, tk = srv.submit(plans[M], r["d"], r["b"], tol=1e-8)
+        assert st == binding.OK
+        res = _wait(srv, [tk], r["L"])[tk]
+        srv.close()
+        assert res.status == binding.OK, res.info
+        assert relerr(res.x, xr) <= 1e-8
+        checks[period] = res.info["checks"]
+        # with a period of 4 no two checks are more than 4 iterations apart
+        if period == 4:
+            assert res.info["checks"] >= res.info["iterations"] // 4
+    print(f"M {M}: checks with the default period {checks[0]}, with period 4 {checks[4]}")
+    assert checks[4] > checks[0]
+
+
+def test_shutdown_cancels_unfinished(plans):
+    """fftcg_server_shutdown: a finished request stays pollable with its
+    result; requests running (they cannot converge: tol 1e-300) and queued
+    end ECANCELED, the running ones with the iterations they ran; they are
+    counted; later submissions are refused with ECANCELED; the plan is free
+    again."""
+    banner("serve-shutdown")
+    srv = binding.Server(memory_budget=1 << 30, max_slots=4)
+    r0 = c4_request(700, 512)
+    st, tk0 = srv.submit(plans[512], r0["d"], r0["b"], tol=1e-8)
+    assert st == binding.OK
+    t0 = time.time()
+    while srv.stats()["completed"] < 1:
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    reqs = [c4_request(701 + k, 512) for k in range(8)]
+    tks = []
+    for r in reqs:
+        st, tk = srv.submit(plans[512], r["d"], r["b"], tol=1e-300, maxit=10 ** 8)
+        assert st == binding.OK
+        tks.append(tk)
+    t0 = time.time()
+    while srv.stats()["in_flight"] < 4:
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    time.sleep(0.05)
+    srv.shutdown()
+    srv.shutdown()  # a second call does nothing
+    st, _ = srv.submit(plans[512], r0["d"], r0["b"])
+    assert st == binding.ECANCELED
+    first = srv.poll(tk0, 256)
+    assert first.status == binding.OK
+    xr, _ = reference_solve(spectrum(512, EPS), r0["d"], r0["b"], 1, route="fft")
+    assert relerr(first.x, xr) <= 1e-8
+    res = [srv.poll(tk, 256) for tk in tks]
+    assert all(v.status == binding.ECANCELED for v in res)
+    ran = [v.info["iterations"] for v in res]
+    assert sum(1 for k in ran if k > 0) == 4   # the four that held slots had run
+    stats = srv.stats()
+    assert stats["canceled"] == 8 and stats["completed"] == 1
+    assert stats["in_flight"] == 0 and stats["queued"] == 0 and stats["bytes_in_use"] == 0
+    srv.close()
+    # no request holds the plan any more
+    plans[512].set_precond(binding.PRECOND_NONE)

@@ -241,3 +241,58 @@ def test_invalid_data(bad):
     for prec, tol, _ in MODES:
         x, info = _solve(plan, inst, prec, tol)
         assert info["status"] == binding.EINVAL
+
+
+@pytest.mark.parametrize("engine", [binding.ENGINE_MULTIPASS, binding.ENGINE_FUSED])
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_breakdown_on_non_finite_start(engine, bad):
+    """A non-finite start vector makes the first true residual non-finite:
+    the solve ends with EBREAKDOWN (both precisions), and the next solve on
+    the same plan is unaffected."""
+    import torch
+    L = 32
+    inst = padded_instance(L, [65, 0])
+    plan = binding.Plan(L, 1, inst["ghat"])
+    plan.set_engine(engine)
+    x0 = np.zeros((L, L))
+    x0[3, 7] = bad
+    for prec, tol, _ in MODES:
+        banner("breakdown", engine, bad, prec)
+        x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+        info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, x0=dev(x0), tol=tol, precision=prec,
+                          raise_on_error=False)
+        assert info["status"] == binding.EBREAKDOWN, info
+        x2, info2 = _solve(plan, inst, prec, tol)
+        assert info2["status"] == binding.OK
+    plan.close()
+
+
+def test_error_target_option():
+    """fftcg_plan_set_error_target: by default the certified target is the
+    residual tolerance; fixed per precision it holds whatever tol is."""
+    inst = c2_instance(2)
+    xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 1, route="fft")
+    plan = binding.Plan(512, 1, inst["ghat"])
+    banner("error-target")
+    x_a, info_a = _solve(plan, inst, binding.FP64, 1e-6)
+    assert info_a["status"] == binding.OK and info_a["error_bound"] <= 1e-6
+    assert relerr(x_a, xr) <= 1e-6
+    plan.set_error_target(binding.FP64, 1e-10)
+    plan.set_error_target(binding.MIXED, 1e-8)
+    x_b, info_b = _solve(plan, inst, binding.FP64, 1e-6)
+    x_c, info_c = _solve(plan, inst, binding.MIXED, 1e-6)
+    print(f"tol 1e-6: tau = tol {info_a['iterations']} iterations (error {relerr(x_a, xr):.2e}); "
+          f"tau 1e-10 {info_b['iterations']} (error {relerr(x_b, xr):.2e}); "
+          f"mixed tau 1e-8 {info_c['iterations']} (error {relerr(x_c, xr):.2e})")
+    assert info_b["status"] == binding.OK and info_b["error_bound"] <= 1e-10
+    assert relerr(x_b, xr) <= 1e-10
+    assert info_b["iterations"] > info_a["iterations"]
+    assert info_c["status"] == binding.OK and info_c["error_bound"] <= 1e-8
+    assert relerr(x_c, xr) <= 1e-8
+    for bad in [(binding.FP64, -1.0), (binding.FP64, 1.0), (2, 1e-8)]:
+        with pytest.raises(binding.FftcgError):
+            plan.set_error_target(*bad)
+    plan.set_error_target(binding.FP64, 0.0)
+    x_d, info_d = _solve(plan, inst, binding.FP64, 1e-6)
+    assert info_d["iterations"] == info_a["iterations"]
+    plan.close()
