@@ -38,3 +38,28 @@ def test_condition_bounds(M, eps, dmin, dmax, expect):
     gh = spectrum(min(M, 256), eps)
     d = np.array([[dmin, dmax]])
     assert kappa_ub(gh, d) == pytest.approx(k, rel=1e-12)
+
+
+@pytest.mark.parametrize("s", [0, 1, 2])
+def test_large_samples_structure(s):
+    """The stored samples of the L = 2048 oracle solutions sit at the seeded
+    positions and carry a certified oracle solution."""
+    import sys
+    sys.path.insert(0, GOLD)
+    from make_c3_samples import sample_positions
+    with open(os.path.join(GOLD, f"padded_L2048_seed{s}_samples.json")) as f:
+        g = json.load(f)
+    assert g["pos"] == sample_positions(s, 2048 * 2048).tolist()
+    assert len(g["x"]) == len(g["pos"]) and np.all(np.isfinite(g["x"]))
+    assert g["bound"] < 1e-12 and g["xnorm"] > 0
+
+
+@pytest.mark.slow
+def test_large_samples_regenerate():
+    """Re-solving the first L = 2048 instance reproduces its stored samples."""
+    from workloads import c3_instance
+    with open(os.path.join(GOLD, "padded_L2048_seed0_samples.json")) as f:
+        g = json.load(f)
+    inst = c3_instance(0)
+    x, info = reference_solve(inst["ghat"], inst["d"], inst["b"], 1, route="fft")
+    assert np.max(np.abs(x.ravel()[g["pos"]] - np.array(g["x"]))) <= 1e-12 * g["xnorm"]

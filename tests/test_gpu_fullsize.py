@@ -1,0 +1,307 @@
+"""Oracle parity on the paths the full-size workloads take.
+
+* fftcg_loadstep called directly on the load-stepped grid (L = 512, 64
+  partial blocks) and the largest one (L = 2048, 1024 partial blocks):
+  bitwise the oracle's argmax, with planted exact ties across partial-block
+  boundaries, inside one thread's grid-stride run and in the last block,
+  broken entries with larger ratios, all-negative ratios, and every entry
+  broken (index -1, d untouched);
+* served requests of the multi-pass classes (M = 512 and 1024) against the
+  oracle's solution run to stagnation, all in one batch;
+* a load-stepped sequence through the server at L = 512 (the multi-pass
+  class and the 64-block argmax): every break is a valid choice for the
+  oracle's solution of that step, and the final x matches the oracle's;
+* the fracture driver at L = 512 with the oracle replaying its breaks;
+* every instance of the periodic L = 64 (100) and padded L = 512 (10)
+  workloads against the oracle, and the three padded L = 2048 instances
+  against sampled entries of the oracle's solutions and the oracle's
+  certification of the GPU solution.
+
+Sec. 2: after each solve the bond whose strain most exceeds its threshold
+breaks; Sec. 3: CG with the eq. (3) product.
+"""
+
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+from paper_1305_3625_amd import binding
+from workloads import (spectrum, c1_instance, c2_instance, c3_instance, c4_request, c5_sequence,
+                       fracture_instance)
+from oracle import (reference_solve, loadstep_argmax, loadstep_valid, fracture_sequence, apply_fft,
+                    lambda_lb, error_bound)
+from gpu_util import dev, host, relerr, banner
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---- fftcg_loadstep ----------------------------------------------------------
+
+def _partials(n):
+    """Blocks of the argmax's first pass (256 entries each, grid-stride)."""
+    return max(1, min(1024, (n + 4095) // 4096))
+
+
+def _ls_case(L, name):
+    n = L * L
+    rng = np.random.default_rng([90, L, sum(map(ord, name))])
+    x = rng.standard_normal((L, L))
+    t = rng.uniform(0.05, 1.0, (L, L))
+    d = rng.uniform(0.5, 1.5, (L, L))
+    d[rng.random((L, L)) < 0.3] = 0.0
+    stride = 256 * _partials(n)
+
+    def tie(idx, v=1.0e3):
+        # equal ratios v, written as different (x, t) pairs scaled by powers
+        # of two so that x / t is exactly v on both sides
+        for k, i in enumerate(idx):
+            s = 2.0 ** (-(k % 3))
+            x.flat[i], t.flat[i], d.flat[i] = v * s, s, 1.0
+
+    def dead(idx, v=4.0e3):
+        for i in idx:
+            x.flat[i], t.flat[i], d.flat[i] = v, 1.0, 0.0
+
+    if name == "cross-block":      # 4095 and 4096 lie in different partial blocks
+        tie([4096, 4095, n - 1])
+    elif name == "last-block":
+        tie([n - 1, n - 257])
+    elif name == "same-thread":    # one thread's consecutive grid-stride entries
+        tie([5 + stride, 5])
+    elif name == "wave-lanes":     # neighbouring lanes and neighbouring waves
+        tie([301, 300, 64, 63])
+    elif name == "dead-first":     # broken entries with larger ratios are skipped
+        dead([50, 99, n - 1])
+        tie([2000, 100])
+    elif name == "negative":       # every ratio negative
+        x[:] = -np.abs(x) - 1e-3
+    elif name == "none-live":
+        d[:] = 0.0
+    return x, t, d
+
+
+LS_CASES = ["cross-block", "last-block", "same-thread", "wave-lanes", "dead-first", "negative", "none-live"]
+LS_EXPECT = {"cross-block": lambda n: 4095, "last-block": lambda n: n - 257, "same-thread": lambda n: 5,
+             "wave-lanes": lambda n: 63, "dead-first": lambda n: 100, "none-live": lambda n: -1}
+
+
+@pytest.mark.parametrize("L", [512, 2048])
+def test_loadstep_direct(L):
+    plan = binding.Plan(L, 1, spectrum(2 * L, 1e-3))
+    n = L * L
+    for name in LS_CASES:
+        banner("loadstep-direct", L, name)
+        x, t, d = _ls_case(L, name)
+        want = loadstep_argmax(x, t, d)
+        if name in LS_EXPECT:
+            assert want == LS_EXPECT[name](n), (name, want)
+        dd = dev(d)
+        got = plan.loadstep(dev(x), dev(t), dd)
+        assert got == want, (L, name, got, want)
+        d_after = d.copy()
+        if want >= 0:
+            d_after.flat[want] = 0.0
+        assert np.array_equal(host(dd), d_after), name
+    plan.close()
+
+
+# ---- the server's multi-pass classes ------------------------------------------
+
+def _wait(srv, tickets, L, timeout=300.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for tk in tickets:
+            if tk not in out:
+                r = srv.poll(tk, L)
+                if r.status != binding.PENDING:
+                    out[tk] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(tickets) - len(out)} requests still pending")
+        time.sleep(0.001)
+    return out
+
+
+@pytest.mark.parametrize("M", [512, 1024])
+def test_served_multipass_vs_oracle(M):
+    L = M // 2
+    gh = spectrum(M, 1e-3)
+    plan = binding.Plan(L, 1, gh)
+    srv = binding.Server(memory_budget=4 << 30)
+    reqs = [c4_request(5000 + 10 * M + k, M) for k in range(4)]
+    banner("served-multipass", M, len(reqs))
+    tks = []
+    for r in reqs:
+        st, tk = srv.submit(plan, r["d"], r["b"], tol=1e-8)
+        assert st == binding.OK
+        tks.append(tk)
+    res = _wait(srv, tks, L)
+    srv.close()
+    for r, tk in zip(reqs, tks):
+        out = res[tk]
+        assert out.status == binding.OK, out.info
+        xr, rinfo = reference_solve(gh, r["d"], r["b"], 1, route="fft")
+        assert rinfo["bound"] < 1e-12
+        err = relerr(out.x, xr)
+        print(f"M {M}: iters {out.info['iterations']} checks {out.info['checks']} error {err:.3e} "
+              f"bound {out.info['error_bound']:.3e}")
+        assert err <= 1e-8
+        assert out.info["error_bound"] <= 1e-8
+    plan.close()
+
+
+def test_served_sequence_L512():
+    L, steps = 512, 30
+    gh = spectrum(2 * L, 1e-3)
+    seq = c5_sequence(11, L=L)
+    plan = binding.Plan(L, 1, gh)
+    srv = binding.Server(memory_budget=4 << 30)
+    banner("served-sequence", L, steps)
+    st, tk = srv.submit_sequence(plan, seq["d"], seq["b"], seq["t"], steps, tol=1e-8)
+    assert st == binding.OK
+    t0 = time.time()
+    while True:
+        r = srv.poll_sequence(tk, L, steps)
+        if r.status != binding.PENDING:
+            break
+        assert time.time() - t0 < 300
+        time.sleep(0.002)
+    srv.close()
+    assert r.status == binding.OK, r.info
+    x_gpu, broken, iters = r.x
+    assert len(set(broken.tolist())) == steps and np.all(broken >= 0)
+    d = seq["d"].copy()
+    x_ref = None
+    for s in range(steps):
+        x_ref, info = reference_solve(gh, d, seq["b"], 1, x0=x_ref, route="fft")
+        # (b = 1 and x ~ b / 33: the 1e-13 residual stop certifies ~3e-12)
+        assert info["bound"] < 1e-11
+        xn = np.linalg.norm(x_ref)
+        # the GPU solve's certified relative error (<= 1e-8) bounds its
+        # max-norm error; the oracle's own bound is added
+        e_inf = 1e-8 * xn / (1 - 1e-8) + info["bound"] * xn
+        j = int(broken[s])
+        assert loadstep_valid(j, x_ref, seq["t"], d, e_inf), (s, j, loadstep_argmax(x_ref, seq["t"], d))
+        d.flat[j] = 0.0
+    err = relerr(x_gpu, x_ref)
+    print(f"L {L} {steps} steps: mean iters {iters.mean():.1f}, final error {err:.3e}")
+    assert err <= 1e-8
+    plan.close()
+
+
+# ---- fracture driver at the benchmarked size -----------------------------------
+
+@pytest.mark.parametrize("prec,tol,precond", [(binding.MIXED, 1e-8, binding.PRECOND_CIRCULANT),
+                                              (binding.FP64, 1e-10, binding.PRECOND_NONE)])
+def test_fracture_L512(prec, tol, precond):
+    import torch
+    L, steps = 512, 10
+    inst = fracture_instance(0, L=L)
+    gh = spectrum(2 * L, 1e-3)
+    plan = binding.Plan(L, 1, gh)
+    plan.set_precond(precond)
+    f = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    banner("fracture-L512", prec, precond)
+    st, broken, dbreak, iters = plan.fracture(inst["k"], dev(inst["t"]), f, steps, tol=tol, precision=prec)
+    assert st == binding.OK
+    _, fo_dbreak, fo_f, ratios = fracture_sequence(gh, inst["k"], inst["t"], steps, 1, replay=broken)
+    t = inst["t"].ravel()
+    for s in range(steps):
+        rho = ratios[s].ravel()
+        k = int(np.argmax(rho))
+        j = int(broken[s])
+        assert np.isfinite(rho[j]), (s, j)
+        einf = 2 * tol * np.linalg.norm(np.where(np.isfinite(rho), rho * t, 0.0))
+        assert rho[j] >= rho[k] - einf * (1.0 / t[j] + 1.0 / t[k]), (s, j, k)
+    np.testing.assert_allclose(dbreak, fo_dbreak, rtol=50 * tol)
+    err = relerr(host(f), fo_f)
+    print(f"prec {prec} pre {precond}: mean iters {iters.mean():.1f}, force error {err:.3e}")
+    assert err <= 10 * tol
+    plan.close()
+
+
+# ---- every instance of the periodic, padded and large workloads -----------------
+
+def _solve(plan, inst, prec, tol):
+    import torch
+    L = inst["L"]
+    x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, tol=tol, precision=prec, raise_on_error=False)
+    return host(x), info
+
+
+def test_periodic_L64_all_instances():
+    gh = c1_instance(0)["ghat"]
+    plan = binding.Plan(64, 0, gh)
+    worst = 0.0
+    banner("periodic-L64-all", 100)
+    for s in range(100):
+        inst = c1_instance(s)
+        xr, rinfo = reference_solve(gh, inst["d"], inst["b"], 0)
+        assert rinfo["bound"] < 1e-12
+        x, info = _solve(plan, inst, binding.FP64, 1e-10)
+        assert info["status"] == binding.OK, (s, info)
+        err = relerr(x, xr)
+        worst = max(worst, err)
+        assert err <= 1e-10, (s, err)
+        assert info["error_bound"] <= 1e-10
+    print(f"periodic L64: worst error over 100 instances {worst:.3e}")
+    plan.close()
+
+
+_C2_REFS = {}
+
+
+def _c2_reference(s):
+    if s not in _C2_REFS:
+        inst = c2_instance(s)
+        xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 1, route="fft")
+        assert rinfo["bound"] < 1e-12
+        _C2_REFS[s] = (inst, xr)
+    return _C2_REFS[s]
+
+
+@pytest.mark.parametrize("prec,tol", [(binding.FP64, 1e-10), (binding.MIXED, 1e-8)])
+def test_padded_L512_all_instances(prec, tol):
+    gh = c2_instance(0)["ghat"]
+    plan = binding.Plan(512, 1, gh)
+    worst = 0.0
+    banner("padded-L512-all", prec)
+    for s in range(10):
+        inst, xr = _c2_reference(s)
+        x, info = _solve(plan, inst, prec, tol)
+        assert info["status"] == binding.OK, (s, info)
+        err = relerr(x, xr)
+        worst = max(worst, err)
+        assert err <= tol, (s, err)
+    print(f"padded L512 prec {prec}: worst error over 10 instances {worst:.3e}")
+    plan.close()
+
+
+@pytest.mark.parametrize("s", [0, 1, 2])
+def test_padded_L2048_against_oracle_samples(s):
+    with open(os.path.join(GOLD, f"padded_L2048_seed{s}_samples.json")) as fh:
+        g = json.load(fh)
+    inst = c3_instance(s)
+    plan = binding.Plan(2048, 1, inst["ghat"])
+    banner("padded-L2048-samples", s)
+    x, info = _solve(plan, inst, binding.MIXED, 1e-8)
+    plan.close()
+    assert info["status"] == binding.OK
+    # sampled entries: |x_i - x*_i| <= ||x - x*|| <= 1e-8 ||x*||, with the
+    # stored solution's own certified error added
+    pos = np.array(g["pos"])
+    gap = np.max(np.abs(x.ravel()[pos] - np.array(g["x"])))
+    assert gap <= (1e-8 + g["bound"]) * g["xnorm"], gap
+    # the whole vector: the oracle's FP64 residual of the GPU solution
+    r = inst["b"] - apply_fft(inst["ghat"], inst["d"], x, 1)
+    rn, xn = np.linalg.norm(r), np.linalg.norm(x)
+    bound = error_bound(rn, xn, lambda_lb(inst["ghat"], inst["d"]))
+    print(f"seed {s}: iters {info['iterations']} checks {info['checks']} max sampled gap "
+          f"{gap / g['xnorm']:.3e} (relative to ||x*||), oracle-certified bound {bound:.3e}")
+    assert bound <= 1e-8
