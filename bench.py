@@ -61,39 +61,62 @@ def fft_flops_nominal(M):
     return 2 * 5 * n * math.log2(n)
 
 
-def cpu_baseline(inst, gpu_iters, max_seconds=20.0):
-    """The oracle's FP64 CG (eq. (3) numpy-FFT product, Listing 2 order) on
-    the same instance for a bounded number of iterations; scaled to solves/s
-    by the GPU's iteration count for that instance."""
-    import numpy as np
-    from oracle import apply_fft, cg
-    mv = lambda v: apply_fft(inst["ghat"], inst["d"], v, 1)  # noqa: E731
+def cpu_baseline(inst, gpu_iters, max_seconds=20.0, direct_offsets=48):
+    """The oracle as it stands, on this host's cores, on the same instance:
+    (1) its FP64 CG with the eq. (3) product (scipy's FFT as a library step,
+    one worker per host core) for a bounded number of iterations, scaled to
+    solves/s by the GPU's iteration count for that instance (the reported
+    value); (2) its direct real-space product (the O(N^2) sum, BLAS on the
+    host cores) timed on a sample of its row separations and extrapolated to
+    a whole product and a whole solve (labelled as such: not run in full)."""
+    from oracle import apply_fft, cg, conv_direct, kernel_table
+    from oracle.operator import host_workers
+    cores = host_workers()
+    mv = lambda v: apply_fft(inst["ghat"], inst["d"], v, 1, workers=cores)  # noqa: E731
     # one product alone sets the iteration budget
     t0 = time.perf_counter()
     mv(inst["b"])
     t_mv = time.perf_counter() - t0
-    iters = max(1, min(8, int(max_seconds / max(t_mv, 1e-3)) - 1))
+    iters = max(1, min(40, int(max_seconds / max(t_mv, 1e-3)) - 1))
     t0 = time.perf_counter()
     _, info = cg(mv, inst["b"], tol=0.0, maxit=iters)
     t = time.perf_counter() - t0
     per_it = t / max(1, info["iterations"])
-    return {
+    out = {
         "value": 1.0 / (per_it * gpu_iters),
         "unit": "solves/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"{info['iterations']} iterations of the oracle's FP64 CG with its numpy-FFT product on "
-                   f"the padded L={inst['L']} instance (seed 0), {per_it:.2f} s/iteration, scaled by the "
-                   f"GPU solve's {gpu_iters} iterations; numpy's FFT and vector ops run on one core"),
+        "sample": (f"{info['iterations']} iterations of the oracle's FP64 CG with its eq. (3) product (scipy FFT, "
+                   f"{cores} workers) on the padded L={inst['L']} instance (seed 0), {per_it:.3f} s/iteration, "
+                   f"scaled by the GPU solve's {gpu_iters} iterations"),
         "seconds": round(t + t_mv, 2),
     }
+    L = inst["L"]
+    g = kernel_table(inst["ghat"])
+    offs = list(range(-(L - 1), L))
+    sample = offs[::max(1, len(offs) // direct_offsets)][:direct_offsets]
+    t0 = time.perf_counter()
+    conv_direct(g, inst["b"], True, offsets=sample)
+    t_s = time.perf_counter() - t0
+    t_direct = t_s * len(offs) / len(sample)
+    out["direct_product_extrapolated"] = {
+        "seconds_per_product": round(t_direct, 2),
+        "solves_per_s": 1.0 / (t_direct * (gpu_iters + 1)),
+        "sample": (f"the oracle's direct real-space product (L^4 = {float(L) ** 4:.3g} multiply-adds as "
+                   f"{len(offs)} Toeplitz GEMMs over row separations) timed on {len(sample)} evenly spaced "
+                   f"separations ({t_s:.2f} s) and scaled by their count; a solve = {gpu_iters} iterations + the "
+                   f"final residual; extrapolated, not run in full"),
+    }
+    return out
 
 
 def cpu_context():
-    """The oracle's FP64 CG with its numpy-FFT product (one host core) on the
-    other workloads, for context: one periodic L = 64 instance (1e-10), one
-    padded L = 512 instance (1e-10), and 4 requests of the serving mix
-    (one per grid size, 1e-8); residual rule on the recursive residual."""
+    """The oracle's FP64 CG with its eq. (3) product (scipy FFT on the host
+    cores) on the other workloads, for context: one periodic L = 64 instance
+    (1e-10), one padded L = 512 instance (1e-10), and 8 requests of the
+    serving mix (two per grid size, 1e-8); residual rule on the recursive
+    residual."""
     import numpy as np
     from oracle import apply_fft, cg
     from workloads import c1_instance, c2_instance, c4_request, spectrum
@@ -106,19 +129,19 @@ def cpu_context():
         out[name] = dict(solves_per_s=round(1.0 / el, 3), iterations=info["iterations"])
     t0 = time.perf_counter()
     its = []
-    for j, M in enumerate((128, 256, 512, 1024)):
+    for j, M in enumerate((128, 256, 512, 1024) * 2):
         r = c4_request(10000 + j, M)
         gh = spectrum(M, 1e-3)
         _, info = cg(lambda v: apply_fft(gh, r["d"], v, 1), r["b"], tol=1e-8)  # noqa: B023
         its.append(info["iterations"])
     el = time.perf_counter() - t0
-    out["serving_sample_4_requests"] = dict(solves_per_s=round(4 / el, 2), iterations_mean=float(np.mean(its)))
+    out["serving_sample_8_requests"] = dict(solves_per_s=round(8 / el, 2), iterations_mean=float(np.mean(its)))
     return out
 
 
 def oracle_certify(insts, xs):
     """Largest certified error bound of the GPU solutions xs, from the
-    oracle's FP64 residual b - A x (numpy-FFT product) and its lambda_lb."""
+    oracle's FP64 residual b - A x (eq. (3) product) and its lambda_lb."""
     import numpy as np
     from oracle import apply_fft, lambda_lb, error_bound
     out = []
@@ -127,6 +150,30 @@ def oracle_certify(insts, xs):
         out.append(error_bound(float(np.linalg.norm(r)), float(np.linalg.norm(x)),
                                lambda_lb(inst["ghat"], inst["d"])))
     return max(out)
+
+
+def hbm_ceiling(nbytes=1 << 30):
+    """Best rate of the library's streaming kernels (read-only, write-only
+    and copy; with and without the non-temporal hint; 1,024 to 8,192
+    workgroups) over 1 GiB buffers, four times the 256 MB last-level cache.
+    Copy counts the bytes read and written."""
+    import torch
+    from paper_1305_3625_amd import binding
+    src = torch.zeros(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for kind, name, mult in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+        best = None
+        for nt in (False, True):
+            for blocks in (1024, 2048, 4096, 8192):
+                ms = binding.stream_probe(kind, dst, src, nbytes, blocks, reps=10, nontemporal=nt)
+                gbps = mult * nbytes / (ms * 1e-3) / 1e9
+                if best is None or gbps > best[0]:
+                    best = (gbps, nt, blocks)
+        out[name] = dict(GBps=round(best[0], 1), nontemporal=best[1], blocks=best[2])
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def _pct(v, q):
@@ -138,25 +185,60 @@ def _pct(v, q):
     return v[k - 1]
 
 
-def serve_bench(n_requests, budget=4 << 30, chunk=10):
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _round(d):
+    """Three decimals for ordinary magnitudes, four significant digits for
+    small ones (error bounds)."""
+    def r(v):
+        if not isinstance(v, float) or not math.isfinite(v):
+            return v
+        return round(v, 3) if abs(v) >= 1.0 else float(f"{v:.4g}")
+    return {k: r(v) for k, v in d.items()}
+
+
+def _stratified(sizes, per_size):
+    """Indices of the first `per_size` requests of each grid size."""
+    out = []
+    for M in sorted(set(int(m) for m in sizes)):
+        out.extend([k for k, m in enumerate(sizes) if int(m) == M][:per_size])
+    return sorted(out)
+
+
+def serve_bench(n_requests, budget=4 << 30, chunk=10, literal=False, full=True, fp64_requests=None,
+                sample_per_size=50):
     """Open-loop serving workload: exponential inter-arrival times (mean
-    0.5 ms), padded grids M in {128, 256, 512, 1024} with p {.4,.3,.2,.1},
-    mixed precision at 1e-8, through the continuous-batching server; then the
-    same schedule through the plain FP64 path one solve at a time.  Latency =
-    completion - scheduled arrival (host monotonic clock)."""
+    0.5 ms), padded grids with p {.4,.3,.2,.1}, mixed precision at 1e-8,
+    through the continuous-batching server; then the same schedule through
+    the plain FP64 path one solve at a time.  Latency = completion -
+    scheduled arrival (host monotonic clock).  The drawn sizes {128, ..., 1024}
+    are the FFT grid M (L = M/2); literal=True reads them as the grid side L
+    (M = 2L, four times the unknowns).  Every served request's certified
+    error bound is collected, and the oracle certifies a stratified sample
+    (the first `sample_per_size` requests of each size) from its FP64
+    residual of the served solution."""
     import numpy as np
     import torch
     from paper_1305_3625_amd import binding
     from workloads import c4_schedule, c4_request, spectrum
-    arrivals, sizes = c4_schedule(n_requests)
-    plans = {M: binding.Plan(M // 2, 1, spectrum(M, 1e-3)) for M in (128, 256, 512, 1024)}
+    arrivals, drawn = c4_schedule(n_requests)
+    sizes = np.array([2 * int(m) if literal else int(m) for m in drawn])
+    grid = sorted(set(sizes.tolist()))
+    plans = {M: binding.Plan(M // 2, 1, spectrum(M, 1e-3)) for M in grid}
     reqs = [c4_request(k, int(M)) for k, M in enumerate(sizes)]
+    sample = set(_stratified(sizes, sample_per_size))
+    progress(f"serving: {n_requests} requests generated")
 
-    def drive(srv, n):
+    def drive(srv, n, keep=None):
         """Releases requests 0..n-1 at their scheduled times; returns the
-        latencies, iteration counts, failures and makespan."""
+        latencies, iteration counts, failures, makespan, every request's
+        certified bound and the solutions of the requests in `keep`."""
         outstanding = {}
-        lat, iters, bad = [], [], 0
+        lat, iters, bounds, bad = [], [], [], 0
+        kept = {}
         t0 = time.perf_counter()
         k = 0
         while k < n or outstanding:
@@ -176,14 +258,17 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
                 t = time.perf_counter() - t0
                 lat.append(t - arrivals[kk])
                 iters.append(res.info["iterations"])
+                bounds.append(res.info["error_bound"])
                 if res.status != binding.OK:
                     bad += 1
+                elif keep is not None and kk in keep:
+                    kept[kk] = res.x
             if not done:
                 nxt = arrivals[k] - (time.perf_counter() - t0) if k < n else 2e-4
                 time.sleep(max(0.0, min(2e-4, nxt)))
-        return lat, iters, bad, time.perf_counter() - t0
+        return lat, iters, bad, time.perf_counter() - t0, bounds, kept
 
-    def run_served(budget=budget, n=len(reqs), warm_n=0):
+    def run_served(budget=budget, n=len(reqs), warm_n=0, keep=None):
         """warm_n > 0: the first warm_n requests of the schedule are served
         first, untimed, on the same server, so that its slots and pinned
         staging buffers have grown to their steady-state number; otherwise
@@ -192,7 +277,7 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
         # warm-up: one request per size (allocates slots, loads kernels)
         tks = []
         for M in plans:
-            r = reqs[list(sizes).index(M)] if M in set(sizes.tolist()) else c4_request(0, M)
+            r = c4_request(0, M)
             st, tk = srv.submit(plans[M], r["d"], r["b"], tol=1e-8)
             tks.append((tk, M // 2))
         for tk, L in tks:
@@ -201,12 +286,13 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
         srv.completed()  # drop the warm-up tickets
         if warm_n:
             drive(srv, warm_n)
-        lat, iters, bad, makespan = drive(srv, n)
+        lat, iters, bad, makespan, bounds, kept = drive(srv, n, keep)
         stats = srv.stats()
         srv.close()
-        return dict(p50_ms=_pct(lat, 50) * 1e3, p99_ms=_pct(lat, 99) * 1e3, solves_per_s=len(lat) / makespan,
-                    makespan_s=makespan, failed=bad, mean_iters=float(np.mean(iters)),
-                    peak_bytes=stats["bytes_in_use"])
+        out = dict(p50_ms=_pct(lat, 50) * 1e3, p99_ms=_pct(lat, 99) * 1e3, solves_per_s=len(lat) / makespan,
+                   makespan_s=makespan, failed=bad, mean_iters=float(np.mean(iters)),
+                   peak_bytes=stats["bytes_in_use"], error_bound_max=float(max(bounds)))
+        return out, kept
 
     def run_closed_loop():
         """Every request released at t = 0: the server's peak throughput, on a
@@ -222,28 +308,33 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
                 if st == binding.OK:
                     left[tk] = r["L"]
             bad = len(reqs) - len(left)
+            eb = 0.0
             while left:
                 done = srv.completed()
                 for tk in done:
-                    if srv.poll(tk, left.pop(tk)).status != binding.OK:
+                    res = srv.poll(tk, left.pop(tk))
+                    eb = max(eb, res.info["error_bound"])
+                    if res.status != binding.OK:
                         bad += 1
                 if not done:
                     time.sleep(2e-4)
             makespan = time.perf_counter() - t0
-            out[label] = dict(solves_per_s=len(reqs) / makespan, makespan_s=makespan, failed=bad)
+            out[label] = dict(solves_per_s=len(reqs) / makespan, makespan_s=makespan, failed=bad,
+                              error_bound_max=eb)
         srv.close()
         return out
 
-    def run_fp64_sequential():
+    def run_fp64_sequential(n):
         dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda")  # noqa: E731
-        lat, bad = [], 0
+        lat, bad, eb = [], 0, 0.0
         # warm-up
         for M, plan in plans.items():
             r = c4_request(0, M)
             x = torch.zeros((M // 2, M // 2), dtype=torch.float64, device="cuda")
             plan.solve(dev(r["d"]), dev(r["b"]), x, tol=1e-8, precision=binding.FP64)
         t0 = time.perf_counter()
-        for k, r in enumerate(reqs):
+        for k in range(n):
+            r = reqs[k]
             now = time.perf_counter() - t0
             if arrivals[k] > now:
                 time.sleep(arrivals[k] - now)
@@ -252,28 +343,37 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10):
             info = plans[r["M"]].solve(dev(r["d"]), dev(r["b"]), x, tol=1e-8, precision=binding.FP64,
                                        raise_on_error=False)
             x.cpu()
+            eb = max(eb, info["error_bound"])
             if info["status"] != binding.OK:
                 bad += 1
             lat.append(time.perf_counter() - t0 - arrivals[k])
         makespan = time.perf_counter() - t0
-        return dict(p50_ms=_pct(lat, 50) * 1e3, p99_ms=_pct(lat, 99) * 1e3, solves_per_s=len(lat) / makespan,
-                    makespan_s=makespan, failed=bad)
+        return dict(requests=n, p50_ms=_pct(lat, 50) * 1e3, p99_ms=_pct(lat, 99) * 1e3,
+                    solves_per_s=len(lat) / makespan, makespan_s=makespan, failed=bad, error_bound_max=eb)
 
-    served = run_served()
-    served_warm = run_served(warm_n=min(len(reqs), 500))
-    closed = run_closed_loop()
-    tight = run_served(budget=64 << 20, n=min(len(reqs), 500))
-    base = run_fp64_sequential()
-    return dict(requests=n_requests, arrival_rate_per_s=round(n_requests / float(arrivals[-1]), 1),
-                budget_bytes=budget,
-                served_mixed={k: (round(v, 3) if isinstance(v, float) else v) for k, v in served.items()},
-                served_mixed_warm={k: (round(v, 3) if isinstance(v, float) else v) for k, v in served_warm.items()},
-                closed_loop_mixed={lab: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
-                                   for lab, d in closed.items()},
-                tight_budget_64MiB_first500={k: (round(v, 3) if isinstance(v, float) else v)
-                                             for k, v in tight.items()},
-                fp64_one_at_a_time={k: (round(v, 3) if isinstance(v, float) else v) for k, v in base.items()},
-                speedup_solves_per_s=round(served["solves_per_s"] / base["solves_per_s"], 2))
+    served, kept = run_served(keep=sample)
+    progress(f"serving: open loop {served['solves_per_s']:.0f} solves/s, p50 {served['p50_ms']:.2f} ms")
+    out = dict(requests=n_requests, sizes="L" if literal else "M", grids_M=grid,
+               arrival_rate_per_s=round(n_requests / float(arrivals[-1]), 1), budget_bytes=budget,
+               served_mixed=_round(served))
+    if full:
+        out["served_mixed_warm"] = _round(run_served(warm_n=min(len(reqs), 500))[0])
+        out["closed_loop_mixed"] = {lab: _round(d) for lab, d in run_closed_loop().items()}
+        out["tight_budget_64MiB_first500"] = _round(run_served(budget=64 << 20, n=min(len(reqs), 500))[0])
+    nb = len(reqs) if fp64_requests is None else min(len(reqs), fp64_requests)
+    base = run_fp64_sequential(nb)
+    progress(f"serving: FP64 one at a time {base['solves_per_s']:.0f} solves/s")
+    out["fp64_one_at_a_time"] = _round(base)
+    out["speedup_solves_per_s"] = round(served["solves_per_s"] / base["solves_per_s"], 2)
+    # the oracle's certification of the sampled served solutions
+    ks = sorted(kept)
+    insts = [dict(reqs[k], ghat=spectrum(reqs[k]["M"], 1e-3)) for k in ks]
+    out["oracle_certified_sample"] = dict(
+        requests=len(ks), per_size=sample_per_size,
+        error_bound_max=oracle_certify(insts, [kept[k] for k in ks]) if ks else None)
+    for p in plans.values():
+        p.close()
+    return out
 
 
 def solve_set_bench(insts, precision, tol):
@@ -311,9 +411,12 @@ def solve_set_bench(insts, precision, tol):
                matvecs_per_s=round((sum(iters) + sum(checks)) / elapsed, 1),
                fft_gflops_nominal=round((sum(iters) + sum(checks)) / elapsed * fft_flops_nominal(M) / 1e9, 2),
                error_bound_max=max(inf["error_bound"] for inf in infos), failed=bad)
+    # the oracle's FP64 residual of every solution, turned into its bound
+    out["oracle_error_bound_max"] = oracle_certify(insts, [X[j].cpu().numpy() for j in range(len(insts))])
     # batched: every instance in flight at once through the server; the
     # first round also creates the slots (cold), the second reuses them (warm)
     srv = binding.Server(memory_budget=4 << 30, max_slots=len(insts))
+    eb = 0.0
     for label in ("cold", "warm"):
         tks = []
         t0 = time.perf_counter()
@@ -327,11 +430,14 @@ def solve_set_bench(insts, precision, tol):
             done = srv.completed()
             for tk in done:
                 left.discard(tk)
-                if srv.poll(tk, L).status != binding.OK:
+                res = srv.poll(tk, L)
+                eb = max(eb, res.info["error_bound"])
+                if res.status != binding.OK:
                     bad += 1
             if not done:
                 time.sleep(2e-4)
         out[f"batched_{label}_solves_per_s"] = round(len(insts) / (time.perf_counter() - t0), 2)
+    out["batched_error_bound_max"] = eb
     out["failed"] = bad
     srv.close()
     plan.close()
@@ -394,45 +500,78 @@ def large_bench(L=4096, steps=2):
     return dict(L=L, M=2 * L, **out)
 
 
-def loadstep_bench(n_seq=64, steps=1000):
+def loadstep_bench(n_seq=64, steps=1000, L=512, prefix_seqs=2, prefix_every=100):
     """Load-stepped sequences (warm-started solves, device argmax break rule),
-    all submitted to the server at once."""
+    all submitted to the server at once.  Every step's certified bound is
+    collected; the oracle certifies each sequence's final solution from its
+    FP64 residual (d with the reported breaks applied).  A sequence is
+    deterministic, so the solution after s steps is the final x of the same
+    sequence submitted with s steps: for the first `prefix_seqs` sequences,
+    such prefixes (every `prefix_every` steps) are run after the timed part,
+    checked to break the same entries, and certified by the oracle too."""
     import numpy as np
     from paper_1305_3625_amd import binding
     from workloads import c5_sequence, spectrum
-    seqs = [c5_sequence(s) for s in range(n_seq)]
-    L = seqs[0]["L"]
-    plan = binding.Plan(L, 1, spectrum(2 * L, seqs[0]["eps"]))
-    srv = binding.Server(memory_budget=4 << 30, max_slots=n_seq)
+    seqs = [c5_sequence(s, L=L) for s in range(n_seq)]
+    gh = spectrum(2 * L, seqs[0]["eps"])
+    plan = binding.Plan(L, 1, gh)
+    srv = binding.Server(memory_budget=8 << 30, max_slots=n_seq)
     st, tk = srv.submit_sequence(plan, seqs[0]["d"], seqs[0]["b"], seqs[0]["t"], 2, tol=1e-8)
     while srv.poll_sequence(tk, L, 2).status == binding.PENDING:
         time.sleep(1e-3)
     srv.completed()
+
+    def run(jobs):
+        """jobs: list of (sequence, steps); returns {job index: result}."""
+        tks = {}
+        for j, (q, n) in enumerate(jobs):
+            st, tk = srv.submit_sequence(plan, q["d"], q["b"], q["t"], n, tol=1e-8)
+            if st != binding.OK:
+                raise SystemExit(f"submit_sequence failed: {binding.STATUS_NAMES.get(st, st)}")
+            tks[tk] = j
+        res = {}
+        while tks:
+            done = srv.completed()
+            for tk in done:
+                j = tks.pop(tk)
+                res[j] = srv.poll_sequence(tk, L, jobs[j][1], bounds=True)
+            if not done:
+                time.sleep(1e-3)
+        return res
+
     t0 = time.perf_counter()
-    tks = {}
-    for q in seqs:
-        st, tk = srv.submit_sequence(plan, q["d"], q["b"], q["t"], steps, tol=1e-8)
-        if st != binding.OK:
-            raise SystemExit(f"submit_sequence failed: {binding.STATUS_NAMES.get(st, st)}")
-        tks[tk] = q
-    iters, bad = [], 0
-    while tks:
-        done = srv.completed()
-        for tk in done:
-            tks.pop(tk)
-            res = srv.poll_sequence(tk, L, steps)
-            if res.status != binding.OK:
-                bad += 1
-            else:
-                iters.extend(res.x[2].tolist())
-        if not done:
-            time.sleep(1e-3)
+    res = run([(q, steps) for q in seqs])
     elapsed = time.perf_counter() - t0
+    bad = sum(r.status != binding.OK for r in res.values())
+    iters = [v for r in res.values() if r.status == binding.OK for v in r.x[2].tolist()]
+    step_bounds = [v for r in res.values() if r.status == binding.OK for v in r.x[3].tolist()]
+
+    def final_inst(q, broken, n):
+        """The last solve of an n-step sequence: the breaks before it applied."""
+        d = q["d"].copy()
+        d.flat[np.asarray(broken[:n - 1])] = 0.0
+        return dict(ghat=gh, d=d, b=q["b"], padded=1)
+
+    ok = [j for j in range(n_seq) if res[j].status == binding.OK]
+    cert_final = oracle_certify([final_inst(seqs[j], res[j].x[1], steps) for j in ok], [res[j].x[0] for j in ok])
+    prefix = None
+    if prefix_seqs > 0 and steps > prefix_every:
+        which = [(j, n) for j in range(min(prefix_seqs, n_seq)) for n in range(prefix_every, steps, prefix_every)]
+        pres = run([(seqs[j], n) for j, n in which])
+        same = all(pres[i].status == binding.OK and np.array_equal(pres[i].x[1], res[j].x[1][:n])
+                   for i, (j, n) in enumerate(which))
+        cert = oracle_certify([final_inst(seqs[j], pres[i].x[1], n) for i, (j, n) in enumerate(which)],
+                              [pres[i].x[0] for i in range(len(which))])
+        jobs = which
+        prefix = dict(sequences=min(prefix_seqs, n_seq), every=prefix_every, solutions=len(jobs),
+                      same_breaks_as_full_run=bool(same), oracle_error_bound_max=cert)
     srv.close()
     plan.close()
-    return dict(sequences=n_seq, steps=steps, L=L, solves=n_seq * steps, makespan_s=round(elapsed, 3),
+    return dict(sequences=n_seq, steps=steps, L=L, M=2 * L, solves=n_seq * steps, makespan_s=round(elapsed, 3),
                 solves_per_s=round(n_seq * steps / elapsed, 1),
-                iterations_per_step_mean=round(float(np.mean(iters)), 2) if iters else None, failed=bad)
+                iterations_per_step_mean=round(float(np.mean(iters)), 2) if iters else None, failed=bad,
+                error_bound_max_all_steps=float(max(step_bounds)) if step_bounds else None,
+                oracle_error_bound_max_final=cert_final, oracle_certified_steps=prefix)
 
 
 def main(argv=None):
@@ -445,8 +584,11 @@ def main(argv=None):
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle certification")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration under rocprofv3)")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests of the open-loop serving workload (0: skip; 20000: the full schedule)")
+    ap.add_argument("--serve-requests", type=int, default=20000,
+                    help="requests of the open-loop serving workload (0: skip; default: the full schedule)")
+    ap.add_argument("--serve-literal-requests", type=int, default=5000,
+                    help="requests of the serving workload with the drawn sizes read as the grid side L "
+                         "(M = 2L; 0: skip)")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the other workloads (periodic L=64 and padded L=512 FP64 sets, load-stepped "
                          "sequences)")
@@ -495,6 +637,7 @@ def main(argv=None):
         if inf["status"] != binding.OK:
             raise SystemExit(f"solve failed: {inf}")
     solves_per_s = a.steps / elapsed
+    progress(f"timed solves: {solves_per_s:.2f} solves/s")
     iters = [inf["iterations"] for inf in infos]
     checks = [inf["checks"] for inf in infos]
     matvecs = sum(iters) + sum(checks)
@@ -514,7 +657,10 @@ def main(argv=None):
         if tr.get("kernel_hash") == kernel_hash() and tr.get("L") == L:
             traffic = tr.get("bytes_per_launch")
 
-    # practical HBM ceiling: a plain 256 MiB device copy, timed with events
+    # practical HBM ceiling: the library's streaming kernels over 1 GiB, and
+    # (for reference, and as the counter calibration under rocprofv3) torch's
+    # own 256 MiB device copy
+    ceiling = hbm_ceiling()
     src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -525,18 +671,25 @@ def main(argv=None):
         dst.copy_(src)
     ev1.record()
     torch.cuda.synchronize()
-    copy_gbps = 2 * src.numel() * 8 * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    torch_copy_gbps = 2 * src.numel() * 8 * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del src, dst
+    copy_gbps = max(ceiling["copy"]["GBps"], torch_copy_gbps)
+    progress(f"HBM probes: {ceiling}")
 
-    # CPU leg: the oracle timed on a bounded sample, and its FP64 residual of
-    # each instance's GPU solution (certified error bound)
+    # the oracle's FP64 residual of each instance's GPU solution, turned into
+    # a certified error bound
+    oracle_bound = None
+    if not a.no_oracle_check:
+        xs = [X[j].cpu().numpy() for j in range(min(len(insts), a.steps))]
+        oracle_bound = oracle_certify(insts, xs)
+
+    # CPU leg: the oracle timed on a bounded sample of the same workload
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(insts[0], infos[0]["iterations"])
+        progress("CPU oracle baseline")
         cpu["other_workloads"] = cpu_context()
-        if not a.no_oracle_check:
-            xs = [X[j].cpu().numpy() for j in range(min(len(insts), a.steps))]
-            cpu["oracle_error_bound_max"] = oracle_certify(insts, xs)
+        progress("CPU oracle context")
 
     # the same workload with the Fourier-space circulant preconditioner (an
     # extension beyond the paper's unpreconditioned CG; reported beside it)
@@ -561,22 +714,31 @@ def main(argv=None):
                    error_bound_max=max(i["error_bound"] for i in pinfos),
                    speedup_vs_plain=round((a.steps / pel) / solves_per_s, 3))
 
-    served = None
+    served = served_literal = None
     if a.serve_requests > 0:
         served = serve_bench(a.serve_requests)
+        progress("serving workload")
+    if a.serve_literal_requests > 0:
+        served_literal = serve_bench(a.serve_literal_requests, literal=True, full=False,
+                                     fp64_requests=min(a.serve_literal_requests, 1000), sample_per_size=25)
+        progress("serving workload, sizes read as L")
 
     other = None
     if not a.no_other:
         from workloads import c1_instance, c2_instance
-        other = {
-            "periodic_L64_fp64_100_instances": solve_set_bench([c1_instance(s) for s in range(100)],
-                                                               binding.FP64, 1e-10),
-            "padded_L512_fp64_10_instances": solve_set_bench([c2_instance(s) for s in range(10)],
-                                                             binding.FP64, 1e-10),
-            "loadstep_L512_mixed": loadstep_bench(a.seq, a.seq_steps) if a.seq > 0 else None,
-            "fracture_L512_mixed_preconditioned": fracture_bench(512, 200, True),
-            "padded_L4096_mixed": large_bench(),
-        }
+        other = {}
+        for name, fn in (
+                ("periodic_L64_fp64_100_instances",
+                 lambda: solve_set_bench([c1_instance(s) for s in range(100)], binding.FP64, 1e-10)),
+                ("padded_L512_fp64_10_instances",
+                 lambda: solve_set_bench([c2_instance(s) for s in range(10)], binding.FP64, 1e-10)),
+                ("loadstep_L512_mixed", lambda: loadstep_bench(a.seq, a.seq_steps) if a.seq > 0 else None),
+                ("loadstep_L1024_mixed",
+                 lambda: loadstep_bench(8, 200, L=1024, prefix_seqs=1, prefix_every=50) if a.seq > 0 else None),
+                ("fracture_L512_mixed_preconditioned", lambda: fracture_bench(512, 200, True)),
+                ("padded_L4096_mixed", large_bench)):
+            other[name] = fn()
+            progress(name)
 
     out = {
         "metric": METRIC,
@@ -608,6 +770,8 @@ def main(argv=None):
             "ms_per_launch": round(passes32[1], 5),
             "copy_GBps": round(copy_gbps, 1),
             "frac_of_copy": round(achieved / copy_gbps, 4),
+            "stream_probes": ceiling,
+            "torch_copy_GBps": round(torch_copy_gbps, 1),
         },
         "cpu_baseline": cpu,
         "iterations_mean": round(float(np.mean(iters)), 2),
@@ -620,9 +784,11 @@ def main(argv=None):
         "product_fp32_GBps": round(bm["apply"] / (sum(passes32) * 1e-3) / 1e9, 1),
         "product_fp64_ms": [round(v, 5) for v in passes64],
         "device_error_bound_max": max(inf["error_bound"] for inf in infos),
+        "oracle_error_bound_max": oracle_bound,
         "plan_ms": round(plan_ms, 2),
         "preconditioned": pre,
         "served": served,
+        "served_literal_L": served_literal,
         "other_workloads": other,
     }
     print(json.dumps(out), flush=True)

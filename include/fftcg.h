@@ -181,6 +181,20 @@ int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d,
                         const double* x, double* y, int reps,
                         double* ms_per_pass, void* stream);
 
+/* fftcg_stream_probe -- measurement aid: the HBM rate of plain streaming
+ * kernels, the practical ceiling of the memory-bound passes.  kind 0 reads
+ * `bytes` from src (16-byte loads, summed; dst is a sink that receives 4
+ * bytes only if the data sums to non-zero), 1 writes zeros to dst, 2 copies
+ * src to dst (`bytes` each, no overlap); with
+ * nontemporal != 0 the loads and stores carry the non-temporal hint.
+ * `blocks` workgroups of 256 threads stride over the buffer.  Times `reps`
+ * back-to-back launches with HIP events on `stream` and stores the mean
+ * device milliseconds per launch in *ms_per_launch (HOST).  src and dst are
+ * DEVICE pointers, 16-byte aligned, `bytes` a positive multiple of 16; src
+ * must hold zeros for kind 0.  Blocks until done.                         */
+int fftcg_stream_probe(int kind, int nontemporal, void* dst, const void* src, size_t bytes,
+                       int blocks, int reps, double* ms_per_launch, void* stream);
+
 /* fftcg_solve -- CG solve of (diag(d) + C) x = b (Sec. 3 Listing 2).
  *   d, b       DEVICE pointers, L*L doubles; d >= 0 and finite, b finite
  *              (checked on the device: FFTCG_EINVAL).
@@ -303,10 +317,14 @@ int fftcg_submit_sequence(fftcg_server_t srv, fftcg_plan_t plan, int precision,
 int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info);
 
 /* fftcg_poll_sequence -- like fftcg_poll for a sequence ticket; also copies
- * the broken indices (HOST pointer, `steps` ints) and the per-step iteration
- * counts (HOST pointer, `steps` ints; may be NULL).                         */
+ * the broken indices (HOST pointer, `steps` ints), the per-step iteration
+ * counts (HOST pointer, `steps` ints) and each step's certified relative
+ * error bound (HOST pointer, `steps` doubles); each may be NULL.  A sequence
+ * is deterministic: the first s steps of a longer sequence on the same
+ * inputs break the same entries and end at bitwise the same x.            */
 int fftcg_poll_sequence(fftcg_server_t srv, uint64_t ticket, double* x,
-                        int* broken, int* step_iters, fftcg_info* info);
+                        int* broken, int* step_iters, double* step_bounds,
+                        fftcg_info* info);
 
 /* fftcg_server_completed -- tickets whose requests finished since the last
  * call, in completion order, so a client polls only those.

@@ -45,14 +45,18 @@ def _check(g, x, padded):
     return L, M
 
 
-def conv_direct(g: np.ndarray, x: np.ndarray, padded: bool) -> np.ndarray:
-    """(C x)(i) = sum_j g_M((i-j) mod M) x_j by the direct real-space sum."""
+def conv_direct(g: np.ndarray, x: np.ndarray, padded: bool, offsets=None) -> np.ndarray:
+    """(C x)(i) = sum_j g_M((i-j) mod M) x_j by the direct real-space sum.
+
+    ``offsets`` (padded grid only; default all of -(L-1)..L-1) restricts the
+    sum to those row separations: a partial sum, used only to time a sample
+    of the full sum's terms on large grids."""
     L, M = _check(g, x, padded)
     x = np.asarray(x, dtype=np.float64)
     y = np.zeros((L, L))
     col = (np.arange(L)[None, :] - np.arange(L)[:, None]) % M  # [j2, i2] -> (i2 - j2) mod M
     if padded:
-        for delta in range(-(L - 1), L):
+        for delta in (range(-(L - 1), L) if offsets is None else offsets):
             T = g[delta % M][col]
             if delta >= 0:
                 y[delta:, :] += x[:L - delta, :] @ T

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD"
 EXPORTS = [
     "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond",
     "fftcg_plan_set_error_target", "fftcg_plan_info",
-    "fftcg_apply", "fftcg_profile_apply", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
+    "fftcg_apply", "fftcg_profile_apply", "fftcg_stream_probe", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_shutdown",
     "fftcg_server_destroy",
@@ -109,7 +109,8 @@ def load(path: str = LIB_PATH):
         "fftcg_submit": (I, [P, P, I, P, P, P, D, I, U64P]),
         "fftcg_submit_sequence": (I, [P, P, I, P, P, P, D, I, I, U64P]),
         "fftcg_poll": (I, [P, ctypes.c_uint64, P, ctypes.POINTER(Info)]),
-        "fftcg_poll_sequence": (I, [P, ctypes.c_uint64, P, P, P, ctypes.POINTER(Info)]),
+        "fftcg_poll_sequence": (I, [P, ctypes.c_uint64, P, P, P, P, ctypes.POINTER(Info)]),
+        "fftcg_stream_probe": (I, [I, I, P, P, S, I, I, ctypes.POINTER(D), P]),
         "fftcg_server_completed": (I, [P, ctypes.POINTER(ctypes.c_uint64), I, ctypes.POINTER(I)]),
         "fftcg_server_get_stats": (I, [P, ctypes.POINTER(ServerStats)]),
         "fftcg_server_shutdown": (I, [P]),
@@ -125,6 +126,17 @@ def load(path: str = LIB_PATH):
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def stream_probe(kind, dst, src, bytes_, blocks, reps=10, nontemporal=False, stream=None):
+    """fftcg_stream_probe: mean device ms per launch of a streaming kernel
+    (kind 0 read, 1 write, 2 copy) over `bytes_` of device buffers."""
+    ms = ctypes.c_double()
+    st = load().fftcg_stream_probe(int(kind), int(bool(nontemporal)), _ptr(dst), _ptr(src), int(bytes_),
+                                   int(blocks), int(reps), ctypes.byref(ms), _stream(stream))
+    if st != OK:
+        raise FftcgError(st, "fftcg_stream_probe")
+    return ms.value
 
 
 def greens_spectrum(L, padded, nu, E, a):
@@ -327,17 +339,20 @@ class Server:
                                ctypes.byref(info))
         return Result(st, x if st in (OK, ENOCONV) else None, info.as_dict())
 
-    def poll_sequence(self, ticket, L, steps):
+    def poll_sequence(self, ticket, L, steps, bounds=False):
+        """x is (x, broken, iters), or (x, broken, iters, step_bounds) with bounds=True."""
         import numpy as np
         x = np.empty((L, L))
         broken = np.empty(steps, dtype=np.int32)
         iters = np.empty(steps, dtype=np.int32)
+        eb = np.empty(steps)
         info = Info()
         st = load().fftcg_poll_sequence(self.h, ctypes.c_uint64(ticket), x.ctypes.data_as(ctypes.c_void_p),
                                         broken.ctypes.data_as(ctypes.c_void_p),
-                                        iters.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info))
+                                        iters.ctypes.data_as(ctypes.c_void_p), eb.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(info))
         if st in (OK, ENOCONV):
-            return Result(st, (x, broken, iters), info.as_dict())
+            return Result(st, (x, broken, iters, eb) if bounds else (x, broken, iters), info.as_dict())
         return Result(st, None, info.as_dict())
 
     def completed(self, cap=4096):

@@ -443,6 +443,35 @@ extern "C" int fftcg_profile_apply(fftcg_plan_t plan, int precision, const doubl
     return rc;
 } FFTCG_ABI_CATCH
 
+extern "C" int fftcg_stream_probe(int kind, int nontemporal, void* dst, const void* src, size_t bytes, int blocks,
+                                  int reps, double* ms_per_launch, void* stream) try {
+    if (kind < 0 || kind > 2 || !ms_per_launch || bytes == 0 || bytes % 16 != 0 || blocks < 1 ||
+        blocks > (1 << 20) || reps < 1)
+        return FFTCG_EINVAL;
+    if (!dst || ((uintptr_t)dst & 15)) return FFTCG_EINVAL;  // kind 0: the sink
+    if (kind != 1 && (!src || ((uintptr_t)src & 15))) return FFTCG_EINVAL;
+    if (kind == 2 && overlap(dst, src, bytes)) return FFTCG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int rc = FFTCG_OK;
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) rc = FFTCG_EDEVICE;
+    if (rc == FFTCG_OK) {
+        launch_stream(kind, nontemporal != 0, blocks, dst, src, bytes, s);  // untimed first launch
+        (void)hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps; ++r) launch_stream(kind, nontemporal != 0, blocks, dst, src, bytes, s);
+        (void)hipEventRecord(ev[1], s);
+        float ms = 0.f;
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+            rc = FFTCG_EDEVICE;
+        else
+            *ms_per_launch = ms / reps;
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+} FFTCG_ABI_CATCH
+
 // ---- solve -------------------------------------------------------------------
 Workspace* fftcg::plan_acquire(fftcg_plan_s* p) {
     std::lock_guard<std::mutex> lk(p->mu);

@@ -61,7 +61,8 @@ struct Request {
     bool in_pinned = true;     // false: pageable (over the pinned cap), staged per slot
     double* pin_x = nullptr;   // pinned result (taken when the solve retires)
     bool x_nomem = false;      // no pinned result buffer could be had
-    int* pin_broken = nullptr; // pinned sequence result
+    int* pin_broken = nullptr; // pinned sequence result: broken indices
+    double* pin_bounds = nullptr; // and each step's certified error bound
     bool has_x0 = false;
     size_t in_bytes = 0;
     int status = FFTCG_PENDING;
@@ -77,6 +78,7 @@ struct Slot {
     double* d = nullptr;
     double* t = nullptr;
     int* broken = nullptr;            // device, one entry per step
+    double* bounds = nullptr;         // device, each step's certified error bound
     SolveState* pin_state = nullptr;  // pinned staging of the state
     double* stage = nullptr;          // pinned staging of pageable request inputs (on first use)
     Request* req = nullptr;
@@ -142,12 +144,14 @@ void free_slot_memory(Slot* s) {
     for (double* v : dv)
         if (v) (void)hipFree(v);
     if (s->broken) (void)hipFree(s->broken);
+    if (s->bounds) (void)hipFree(s->bounds);
     if (s->pin_state) (void)hipHostFree(s->pin_state);
     if (s->stage) (void)hipHostFree(s->stage);
     s->stage = nullptr;
     if (s->ev_retire) (void)hipEventDestroy(s->ev_retire);
     s->x = s->b = s->d = s->t = nullptr;
     s->broken = nullptr;
+    s->bounds = nullptr;
     s->pin_state = nullptr;
     s->ev_retire = nullptr;
     s->ws.reset();
@@ -196,6 +200,7 @@ bool add_slot(fftcg_server_s* srv, Class* c) {
     ok = ok && hipMalloc(&s->x, n * 8) == hipSuccess && hipMalloc(&s->b, n * 8) == hipSuccess &&
          hipMalloc(&s->d, n * 8) == hipSuccess && hipMalloc(&s->t, n * 8) == hipSuccess &&
          hipMalloc(&s->broken, sizeof(int) * kMaxSteps) == hipSuccess &&
+         hipMalloc(&s->bounds, sizeof(double) * kMaxSteps) == hipSuccess &&
          hipHostMalloc((void**)&s->pin_state, sizeof(SolveState), hipHostMallocDefault) == hipSuccess &&
          hipEventCreateWithFlags(&s->ev_retire, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
@@ -364,7 +369,7 @@ bool progress(fftcg_server_s* srv, Class* c) {
         if (ok && q->steps > 0) {
             // the load step of this solve, on the device
             launch_loadstep(s->x, s->t, s->d, (int)q->n, s->ws->ls_pv, s->ws->ls_pi, s->broken + s->step,
-                            c->stream);
+                            c->stream, &s->ws->st->bound, s->bounds + s->step);
             if (s->step + 1 < q->steps) {
                 q->step_iters.push_back(__atomic_load_n(hs + 3, __ATOMIC_RELAXED));
                 s->step += 1;
@@ -386,8 +391,12 @@ bool progress(fftcg_server_s* srv, Class* c) {
             else
                 q->x_nomem = true;
             if (q->steps > 0)
+            {
                 (void)hipMemcpyAsync(q->pin_broken, s->broken, sizeof(int) * q->steps, hipMemcpyDeviceToHost,
                                      c->stream);
+                (void)hipMemcpyAsync(q->pin_bounds, s->bounds, sizeof(double) * q->steps, hipMemcpyDeviceToHost,
+                                     c->stream);
+            }
         }
         (void)hipEventRecord(s->ev_retire, c->stream);
         s->retiring = true;
@@ -541,8 +550,10 @@ void free_request_buffers(fftcg_server_s* srv, Request* q) {
     pin_put(srv, q->pin_in, q->in_bytes, true, q->in_pinned);
     pin_put(srv, q->pin_x, q->n * 8, false, true);
     pin_put(srv, q->pin_broken, sizeof(int) * (size_t)q->steps, false, true);
+    pin_put(srv, q->pin_bounds, sizeof(double) * (size_t)q->steps, false, true);
     q->pin_in = q->pin_x = nullptr;
     q->pin_broken = nullptr;
+    q->pin_bounds = nullptr;
 }
 
 }  // namespace
@@ -598,8 +609,11 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     q->in_bytes = n * 8 * (2 + (x0 ? 1 : 0) + (t ? 1 : 0));
     bool pinned = true;
     q->pin_in = (double*)pin_get(srv, q->in_bytes, true, &q->in_pinned);
-    if (steps > 0) q->pin_broken = (int*)pin_get(srv, sizeof(int) * steps, false, &pinned);
-    if (!q->pin_in || (steps > 0 && !q->pin_broken)) {
+    if (steps > 0) {
+        q->pin_broken = (int*)pin_get(srv, sizeof(int) * steps, false, &pinned);
+        q->pin_bounds = (double*)pin_get(srv, sizeof(double) * steps, false, &pinned);
+    }
+    if (!q->pin_in || (steps > 0 && (!q->pin_broken || !q->pin_bounds))) {
         free_request_buffers(srv, q.get());
         return FFTCG_ENOMEM;
     }
@@ -659,7 +673,7 @@ extern "C" int fftcg_submit_sequence(fftcg_server_t srv, fftcg_plan_t plan, int 
 } FFTCG_ABI_CATCH
 
 static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
-                       fftcg_info* info, bool seq) {
+                       double* step_bounds, fftcg_info* info, bool seq) {
     if (!srv) return FFTCG_EINVAL;
     std::unique_ptr<Request> q;
     {
@@ -675,6 +689,7 @@ static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* brok
     if (st == FFTCG_OK || st == FFTCG_ENOCONV) {
         if (x) memcpy(x, q->pin_x, q->n * 8);
         if (seq && broken) memcpy(broken, q->pin_broken, sizeof(int) * q->steps);
+        if (seq && step_bounds) memcpy(step_bounds, q->pin_bounds, sizeof(double) * q->steps);
         if (seq && step_iters)
             for (int i = 0; i < q->steps; ++i) step_iters[i] = i < (int)q->step_iters.size() ? q->step_iters[i] : -1;
     }
@@ -684,12 +699,12 @@ static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* brok
 }
 
 extern "C" int fftcg_poll(fftcg_server_t srv, uint64_t ticket, double* x, fftcg_info* info) try {
-    return poll_common(srv, ticket, x, nullptr, nullptr, info, false);
+    return poll_common(srv, ticket, x, nullptr, nullptr, nullptr, info, false);
 } FFTCG_ABI_CATCH
 
 extern "C" int fftcg_poll_sequence(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
-                                   fftcg_info* info) try {
-    return poll_common(srv, ticket, x, broken, step_iters, info, true);
+                                   double* step_bounds, fftcg_info* info) try {
+    return poll_common(srv, ticket, x, broken, step_iters, step_bounds, info, true);
 } FFTCG_ABI_CATCH
 
 extern "C" int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap, int* n) try {

@@ -211,13 +211,15 @@ def test_loadstep_sequence_replay():
     assert st == binding.OK
     t0 = time.time()
     while True:
-        r = srv.poll_sequence(tk, L, steps)
+        r = srv.poll_sequence(tk, L, steps, bounds=True)
         if r.status != binding.PENDING:
             break
         assert time.time() - t0 < 120
         time.sleep(0.002)
     assert r.status == binding.OK, r.info
-    x_gpu, broken, iters = r.x
+    x_gpu, broken, iters, step_bounds = r.x
+    # every step's solve was certified to the target
+    assert np.all(step_bounds > 0.0) and np.all(step_bounds <= 1e-8)
     assert len(set(broken.tolist())) == steps and np.all(broken >= 0)
     # replay: the oracle solves each step with the GPU's sequence of breaks
     d = seq["d"].copy()

@@ -157,3 +157,17 @@ def test_shape_errors():
         conv_direct(g, np.zeros((8, 8)), True)
     with pytest.raises(ValueError):
         conv_direct(g, np.zeros((4, 4)), False)
+
+
+def test_conv_direct_offsets_partition():
+    """Partial sums over a partition of the row separations add up to the
+    whole direct sum (the timing sample of the CPU baseline uses them)."""
+    from oracle import conv_direct, kernel_table
+    from workloads import spectrum
+    L = 12
+    g = kernel_table(spectrum(2 * L, 1e-3))
+    x = np.random.default_rng([91, 0]).standard_normal((L, L))
+    full = conv_direct(g, x, True)
+    offs = list(range(-(L - 1), L))
+    parts = conv_direct(g, x, True, offsets=offs[::2]) + conv_direct(g, x, True, offsets=offs[1::2])
+    np.testing.assert_allclose(parts, full, rtol=0, atol=1e-13 * np.abs(full).max())
