@@ -1,9 +1,11 @@
 // Device building blocks of the FFT engine for gfx950 (wave64).
 //
 // * cx<T>        complex value in registers (T = float or double).
-// * dft<R,DIR>   radix-R DFT (R = 1, 2, 4, 8, 16) on R registers, as radix-2
-//                decimation-in-frequency layers with compile-time twiddles;
-//                HALF_IN skips the upper half of the inputs (known zeros).
+// * dft<R,DIR>   radix-R DFT (R = 1, 2, 4, 8, 16) on R registers: radix 16
+//                as 4 x 4 with the inner twiddles' scales folded into FMAs,
+//                smaller radices as radix-2 decimation-in-frequency layers
+//                with compile-time twiddles; HALF_IN skips the upper half of
+//                the inputs (known zeros).
 // * stages<...>  Stockham self-sorting FFT of length N held by N/E threads of
 //                E = min(N, 16) values each.  Butterfly b of a radix-R stage
 //                reads positions b + r N/R and writes
@@ -127,11 +129,108 @@ __host__ __device__ constexpr int brev(int i, int bits) {
     return bits == 0 ? 0 : (((i & 1) << (bits - 1)) | brev(i >> 1, bits - 1));
 }
 
+// Fused multiply-add in the precision of its operands (one rounding).
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// a * (DIR i)
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> muli(cx<T> a) {
+    return DIR > 0 ? mkc(-a.y, a.x) : mkc(a.y, -a.x);
+}
+
+// Radix-4 DFT of x0 + s1 u1, x2, s1 u3 (HALF: x2 = u3 = 0; NEG3: the third
+// input is -s1 u3), Y[k] = sum_n x_n (DIR i)^(n k), written to y[0..3].
+// s1 scales the odd inputs and is folded into the output FMAs; p0 = x0 + x2
+// and q0 = x0 - x2 come from the caller (who may fold a scale of x2 there).
+template <typename T, int DIR, bool NEG3>
+__device__ __forceinline__ void r4_tail(cx<T> p0, cx<T> q0, cx<T> u1, cx<T> u3, T s1, cx<T>* y0, cx<T>* y1,
+                                        cx<T>* y2, cx<T>* y3) {
+    // r = s1 (u1 +- u3), q = s1 (u1 -+ u3)
+    const cx<T> r = NEG3 ? u1 - u3 : u1 + u3;
+    const cx<T> q = NEG3 ? u1 + u3 : u1 - u3;
+    const T d = T(DIR);
+    *y0 = mkc(fmat(s1, r.x, p0.x), fmat(s1, r.y, p0.y));
+    *y2 = mkc(fmat(-s1, r.x, p0.x), fmat(-s1, r.y, p0.y));
+    // y1 = q0 + (DIR i) s1 q, y3 = q0 - (DIR i) s1 q
+    *y1 = mkc(fmat(-d * s1, q.y, q0.x), fmat(d * s1, q.x, q0.y));
+    *y3 = mkc(fmat(d * s1, q.y, q0.x), fmat(-d * s1, q.x, q0.y));
+}
+
+// Radix-16 DFT as 4 x 4 (index r = n1 + 4 n2, k = k1 + 4 k2):
+//   A[n1][k1] = radix-4 over n2 of v[n1 + 4 n2],
+//   B[n1][k1] = A[n1][k1] w^(n1 k1),  w = exp(DIR 2 pi i / 16),
+//   X[k1 + 4 k2] = radix-4 over n1 of B[n1][k1].
+// Every nontrivial w^e is a real scale times a two-operation rotation:
+//   w^1 = c8 (1 + t8 Di), w^3 = c8 (t8 + Di), w^9 = -w^1,
+//   w^2 = c2 (1 + Di), w^6 = c2 (-1 + Di), w^4 = Di  (Di = DIR i),
+// c8 = cos(pi/8), t8 = tan(pi/8), c2 = cos(pi/4); the scales of one column
+// k1 are folded into the FMAs of its second radix-4, so a butterfly costs 144
+// real operations (112 with the upper half of the inputs zero).
+template <typename T, int DIR, bool HALF_IN>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+    const T c8 = T(0.92387953251128675613);  // cos(pi/8)
+    const T t8 = T(0.41421356237309504880);  // tan(pi/8)
+    const T c2 = T(0.70710678118654752440);  // cos(pi/4)
+    const T d = T(DIR);
+    cx<T> A[4][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+        const cx<T> x0 = v[n1], x1 = v[n1 + 4];
+        if constexpr (HALF_IN) {
+            const cx<T> ix1 = muli<T, DIR>(x1);
+            A[n1][0] = x0 + x1;
+            A[n1][2] = x0 - x1;
+            A[n1][1] = x0 + ix1;
+            A[n1][3] = x0 - ix1;
+        } else {
+            const cx<T> x2 = v[n1 + 8], x3 = v[n1 + 12];
+            const cx<T> p = x0 + x2, q = x0 - x2, r = x1 + x3, s = muli<T, DIR>(x1 - x3);
+            A[n1][0] = p + r;
+            A[n1][2] = p - r;
+            A[n1][1] = q + s;
+            A[n1][3] = q - s;
+        }
+    }
+    // unscaled rotations: U = B / scale
+    auto rot1 = [&](cx<T> a) { return mkc(fmat(-d * t8, a.y, a.x), fmat(d * t8, a.x, a.y)); };  // w^1 / c8
+    auto rot3 = [&](cx<T> a) { return mkc(fmat(t8, a.x, -d * a.y), fmat(t8, a.y, d * a.x)); };  // w^3 / c8
+    auto rot2 = [&](cx<T> a) { return mkc(a.x - d * a.y, a.y + d * a.x); };                   // w^2 / c2
+    auto rot6 = [&](cx<T> a) { return mkc(-a.x - d * a.y, -a.y + d * a.x); };                 // w^6 / c2
+    // k1 = 0: no twiddles
+    {
+        const cx<T> p0 = A[0][0] + A[2][0], q0 = A[0][0] - A[2][0];
+        r4_tail<T, DIR, false>(p0, q0, A[1][0], A[3][0], T(1), &v[0], &v[4], &v[8], &v[12]);
+    }
+    // k1 = 1: w^0, c8 rot1, c2 rot2, c8 rot3
+    {
+        const cx<T> u2 = rot2(A[2][1]);
+        const cx<T> p0 = mkc(fmat(c2, u2.x, A[0][1].x), fmat(c2, u2.y, A[0][1].y));
+        const cx<T> q0 = mkc(fmat(-c2, u2.x, A[0][1].x), fmat(-c2, u2.y, A[0][1].y));
+        r4_tail<T, DIR, false>(p0, q0, rot1(A[1][1]), rot3(A[3][1]), c8, &v[1], &v[5], &v[9], &v[13]);
+    }
+    // k1 = 2: w^0, c2 rot2, w^4 = Di, c2 rot6
+    {
+        const cx<T> u2 = muli<T, DIR>(A[2][2]);
+        const cx<T> p0 = A[0][2] + u2, q0 = A[0][2] - u2;
+        r4_tail<T, DIR, false>(p0, q0, rot2(A[1][2]), rot6(A[3][2]), c2, &v[2], &v[6], &v[10], &v[14]);
+    }
+    // k1 = 3: w^0, c8 rot3, c2 rot6, -c8 rot1 (w^9 = -w^1)
+    {
+        const cx<T> u2 = rot6(A[2][3]);
+        const cx<T> p0 = mkc(fmat(c2, u2.x, A[0][3].x), fmat(c2, u2.y, A[0][3].y));
+        const cx<T> q0 = mkc(fmat(-c2, u2.x, A[0][3].x), fmat(-c2, u2.y, A[0][3].y));
+        r4_tail<T, DIR, true>(p0, q0, rot3(A[1][3]), rot1(A[3][3]), c8, &v[3], &v[7], &v[11], &v[15]);
+    }
+}
+
 // In-register radix-R DFT, X[k] = sum_r v[r] exp(DIR 2 pi i r k / R).
 template <typename T, int R, int DIR, bool HALF_IN>
 __device__ __forceinline__ void dft(cx<T>* v) {
     if constexpr (R == 1) {
         return;
+    } else if constexpr (R == 16) {
+        dft16<T, DIR, HALF_IN>(v);
     } else {
         cx<T> t[R];
 #pragma unroll
