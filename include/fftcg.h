@@ -276,6 +276,9 @@ typedef struct {
     int    refresh_period;    /* MIXED FP64 check period (0: 50)            */
     int    queue_cap;         /* pending requests (0: 1<<20)                */
     int    device;            /* HIP device ordinal                         */
+    int    graphs;            /* 0: each multi-pass chunk shape (running
+                                 slots) is captured once as a HIP graph and
+                                 replayed; -1: kernels launched directly    */
 } fftcg_server_opts;
 
 typedef struct {

@@ -61,7 +61,7 @@ class Info(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int),
                 ("chunk_iters", ctypes.c_int), ("refresh_period", ctypes.c_int),
-                ("queue_cap", ctypes.c_int), ("device", ctypes.c_int)]
+                ("queue_cap", ctypes.c_int), ("device", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class ServerStats(ctypes.Structure):
@@ -303,9 +303,10 @@ class Server:
     """fftcg_server_*: continuous-batching solve server (host arrays)."""
 
     def __init__(self, memory_budget=4 << 30, max_slots=0, chunk_iters=0, refresh_period=0,
-                 queue_cap=0, device=0):
+                 queue_cap=0, device=0, graphs=True):
         lib = load()
-        o = ServerOpts(memory_budget, max_slots, chunk_iters, refresh_period, queue_cap, device)
+        o = ServerOpts(memory_budget, max_slots, chunk_iters, refresh_period, queue_cap, device,
+                       0 if graphs else -1)
         h = ctypes.c_void_p()
         st = lib.fftcg_server_create(ctypes.byref(o), ctypes.byref(h))
         if st != OK:

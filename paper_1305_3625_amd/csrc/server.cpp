@@ -103,6 +103,8 @@ struct Class {
     int next_ev = 0;
     size_t footprint = 0;  // device bytes per slot
     int refresh = 50;      // MIXED: iterations between FP64 checks
+    // multi-pass chunks captured as HIP graphs, by (running slots, preconditioned)
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
 };
 
 }  // namespace
@@ -247,6 +249,8 @@ int make_class(fftcg_server_s* srv, fftcg_plan_s* plan, int precision, Class** o
 
 void destroy_class(Class* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
     for (auto& s : c->slots) free_slot_memory(s.get());
     if (c->d_table) (void)hipFree(c->d_table);
     if (c->h_table) (void)hipHostFree(c->h_table);
@@ -330,6 +334,44 @@ void finish_request(fftcg_server_s* srv, Request* q, int status, const SolveStat
     else
         srv->stats.failed += 1;
     q->plan->refs.fetch_sub(1);
+}
+
+// One chunk of the multi-pass engine over slots 0..nsl-1: chunk_iters CG
+// iterations, then an FP64-check sequence (kernel launches only).
+void launch_chunk(fftcg_server_s* srv, Class* c, int nsl, bool pcg) {
+    const EngineOps* ops = c->plan->ops;
+    const auto iter = pcg ? ops->iter_pcg : ops->iter;
+    const auto check = pcg ? ops->check_pcg : ops->check;
+    for (int k = 0; k < srv->opts.chunk_iters; ++k)
+        iter(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+    check(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+}
+
+// The chunk for nsl running slots as an instantiated HIP graph, captured from
+// the class's stream the first time that shape runs (every kernel argument
+// is fixed per class and shape: the slot table is device-resident, so a
+// replay sees the slots' current contents).  A chunk is some forty kernel
+// launches; replayed as one graph it costs the scheduler thread a single
+// launch, which keeps the small classes' GPU work from waiting on the host.
+// nullptr if capture or instantiation fails (the caller then launches
+// directly).
+hipGraphExec_t chunk_graph(fftcg_server_s* srv, Class* c, int nsl, bool pcg) {
+    const auto key = std::make_pair(nsl, pcg ? 1 : 0);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) return it->second;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    launch_chunk(srv, c, nsl, pcg);
+    if (hipStreamEndCapture(c->stream, &g) != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return nullptr;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess || !ex) return nullptr;
+    c->graphs[key] = ex;
+    return ex;
 }
 
 // Scheduler work for one class; true while it has queued or running work.
@@ -441,13 +483,12 @@ bool progress(fftcg_server_s* srv, Class* c) {
             // one workgroup per slot runs the chunk's iterations and checks
             fused_launch(c->plan, c->precision, c->d_table, nsl, srv->opts.chunk_iters, c->stream);
         } else {
-            const EngineOps* ops = c->plan->ops;
             const bool pcg = c->plan->precond == FFTCG_PRECOND_CIRCULANT;
-            const auto iter = pcg ? ops->iter_pcg : ops->iter;
-            const auto check = pcg ? ops->check_pcg : ops->check;
-            for (int k = 0; k < srv->opts.chunk_iters; ++k)
-                iter(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
-            check(c->precision, c->plan->tabs, c->d_table, nsl, c->plan->stride, c->stream);
+            hipGraphExec_t ex = srv->opts.graphs >= 0 ? chunk_graph(srv, c, nsl, pcg) : nullptr;
+            if (!ex || hipGraphLaunch(ex, c->stream) != hipSuccess) {
+                (void)hipGetLastError();  // a failed capture or replay falls back to direct launches
+                launch_chunk(srv, c, nsl, pcg);
+            }
         }
         (void)hipEventRecord(c->ev[c->next_ev], c->stream);
         c->next_ev ^= 1;
@@ -561,7 +602,7 @@ void free_request_buffers(fftcg_server_s* srv, Request* q) {
 extern "C" int fftcg_server_create(const fftcg_server_opts* opts, fftcg_server_t* out) try {
     if (!opts || !out) return FFTCG_EINVAL;
     if (opts->memory_budget == 0 || opts->max_slots < 0 || opts->chunk_iters < 0 || opts->refresh_period < 0 ||
-        opts->queue_cap < 0)
+        opts->queue_cap < 0 || (opts->graphs != 0 && opts->graphs != -1))
         return FFTCG_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opts->device < 0 || opts->device >= ndev) return FFTCG_EDEVICE;

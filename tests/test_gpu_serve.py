@@ -306,3 +306,37 @@ def test_shutdown_cancels_unfinished(plans):
     srv.close()
     # no request holds the plan any more
     plans[512].set_precond(binding.PRECOND_NONE)
+
+
+def test_graph_replay_equals_direct_launches(plans):
+    """Multi-pass chunks replayed from captured HIP graphs give bitwise the
+    same solutions, iteration and check counts as the same chunks launched
+    kernel by kernel, over several rounds of a changing mix (graph shapes
+    are reused across rounds with different slot contents)."""
+    banner("serve-graphs")
+    p1024 = binding.Plan(512, 1, spectrum(1024, EPS))
+    pl = {**plans, 1024: p1024}
+    reqs = [c4_request(800 + k, M) for k, M in enumerate([256, 512, 1024, 512, 256, 1024, 512, 256])]
+    out = {}
+    for graphs in (False, True):
+        srv = binding.Server(memory_budget=2 << 30, graphs=graphs)
+        res = []
+        for rnd in range(3):
+            batch = reqs[rnd:] + reqs[:rnd]  # a different order, so slots hold different requests
+            tks = []
+            Ls = {}
+            for r in batch:
+                st, tk = srv.submit(pl[r["M"]], r["d"], r["b"], tol=1e-8)
+                assert st == binding.OK
+                tks.append(tk)
+                Ls[tk] = r["L"]
+            got = _wait(srv, tks, Ls)
+            for r, tk in zip(batch, tks):
+                assert got[tk].status == binding.OK, got[tk].info
+                res.append((id(r), got[tk].x, got[tk].info["iterations"], got[tk].info["checks"]))
+        srv.close()
+        out[graphs] = res
+    for (ia, xa, ita, ca), (ib, xb, itb, cb) in zip(out[False], out[True]):
+        assert ia == ib and ita == itb and ca == cb
+        assert np.array_equal(xa, xb)
+    p1024.close()
