@@ -38,10 +38,11 @@ def test_apply_small_direct(L, padded, engine):
     d, x = _inputs(L, padded, 0)
     ref = apply_direct(g, d, x, padded)
     banner("apply", L, padded, engine)
-    for prec, tol in ((binding.FP64, 1e-13), (binding.MIXED, 2e-6)):
+    for prec, tol in ((binding.FP64, 1e-13), (binding.MIXED, 1e-6)):
         y = dev(np.zeros((L, L)))
         plan.apply(dev(d), dev(x), y, precision=prec)
         err = relerr(host(y), ref)
+        print(f"apply L {L} pad {padded} engine {engine} prec {prec}: relative error {err:.3e}")
         assert err <= tol, (prec, err)
 
 
@@ -58,7 +59,9 @@ def test_apply_large_fft_route(L, padded):
     plan.apply(dev(d), dev(x), y, precision=binding.FP64)
     assert relerr(host(y), ref) <= 1e-13
     plan.apply(dev(d), dev(x), y, precision=binding.MIXED)
-    assert relerr(host(y), ref) <= 2e-6
+    err = relerr(host(y), ref)
+    print(f"apply-large L {L} pad {padded} mixed: relative error {err:.3e}")
+    assert err <= 1e-6
 
 
 def test_apply_sampled_direct_full_size():

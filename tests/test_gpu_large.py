@@ -33,11 +33,13 @@ def test_apply_sampled_M8192(L, padded):
     cols = list(rng.integers(0, L, 34)) + [0, L - 1, L - 1, 0, L // 2, L - 2]
     ref = apply_direct_at(g, d, x, padded, rows, cols)
     scale = np.abs(x).max() * np.abs(g).sum()
-    for prec, tol in ((binding.FP64, 1e-13), (binding.MIXED, 3e-6)):
+    for prec, tol in ((binding.FP64, 1e-13), (binding.MIXED, 1e-6)):
         y = dev(np.zeros((L, L)))
         plan.apply(dev(d), dev(x), y, precision=prec)
         yh = host(y)
-        assert np.max(np.abs(yh[rows, cols] - ref)) <= tol * scale, prec
+        e = np.max(np.abs(yh[rows, cols] - ref)) / scale
+        print(f"apply M8192 L {L} pad {padded} prec {prec}: max sampled error / (max|x| sum|g|) {e:.3e}")
+        assert e <= tol, prec
         del y
     plan.close()
 
