@@ -88,10 +88,27 @@ def _jobs(build_dir, extra):
                os.path.join(CSRC, "fused_inst.hip"), "-o", obj(f"fused_{m}_{pad}")]
 
 
+# host-side sanitizers (device code is built as usual): -Xarch_host keeps
+# each flag off the gfx950 compilation
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+SANITIZE_LIB = os.path.join(BUILD, "asan", "libfftcg.so")
+
+
 def build(jobs: int | None = None, verbose: bool = False, extra_flags=(), lib_path: str = LIB,
-          build_dir: str = BUILD) -> str:
+          build_dir: str = BUILD, sanitize: bool = False) -> str:
     """Compiles every source (always) and links lib_path.  extra_flags are
-    passed to every compile (e.g. -D switches of tuning variants)."""
+    passed to every compile (e.g. -D switches of tuning variants).  With
+    sanitize, the host code is built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (default output _build/asan/libfftcg.so; the
+    runtime must be preloaded, see tests/test_sanitize.py)."""
+    if sanitize:
+        extra_flags = list(extra_flags) + SANITIZE_FLAGS
+        if lib_path == LIB:
+            lib_path = SANITIZE_LIB
+        if build_dir == BUILD:
+            build_dir = os.path.join(BUILD, "asan_obj")
+        os.makedirs(os.path.dirname(lib_path), exist_ok=True)
     os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     cmds = list(_jobs(build_dir, list(extra_flags)))
@@ -101,7 +118,8 @@ def build(jobs: int | None = None, verbose: bool = False, extra_flags=(), lib_pa
                 print(out)
     objs = [c[-1] for c in cmds]
     tmp = lib_path + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-fPIC", "-o", tmp,
+    san = ["-fsanitize=address,undefined", "-shared-libsan"] if sanitize else []
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-fPIC", *san, "-o", tmp,
           *objs, "-lpthread"])
     os.replace(tmp, lib_path)
     return lib_path
@@ -111,8 +129,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("--sanitize", action="store_true",
+                    help="host code with AddressSanitizer + UBSan, into _build/asan/libfftcg.so")
     a = ap.parse_args(argv)
-    print(build(a.jobs, a.verbose))
+    print(build(a.jobs, a.verbose, sanitize=a.sanitize))
 
 
 if __name__ == "__main__":
