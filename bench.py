@@ -31,14 +31,18 @@ METRIC = "FFT-CG solves/s + HBM GB/s at L=2048; served p50/p99 latency vs plain 
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_col_M4096_fp32_traffic.json")
 KERNEL_SOURCES = ["paper_1305_3625_amd/csrc/fftcg_kernels.hpp", "paper_1305_3625_amd/csrc/fftcg_dev.hpp",
-                  "paper_1305_3625_amd/csrc/engine_inst.hip", "paper_1305_3625_amd/build.py"]
+                  "paper_1305_3625_amd/csrc/engine_inst.hip"]
 
 
 def kernel_hash():
+    """Hash of what determines the multi-pass engine's code: its sources, the
+    compiler flags and the per-size radix table of the build."""
+    from paper_1305_3625_amd import build
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    h.update(repr((build.CXXFLAGS, build.ENGINE_SIZES, build.ARCH)).encode())
     return h.hexdigest()[:16]
 
 
@@ -154,23 +158,24 @@ def oracle_certify(insts, xs):
 
 def hbm_ceiling(nbytes=1 << 30):
     """Best rate of the library's streaming kernels (read-only, write-only
-    and copy; with and without the non-temporal hint; 1,024 to 8,192
-    workgroups) over 1 GiB buffers, four times the 256 MB last-level cache.
-    Copy counts the bytes read and written."""
+    and copy; with and without the non-temporal hint; 1,024 to 16,384
+    workgroups) over 1 GiB buffers, four times the 256 MB last-level cache,
+    with every variant's rate.  Copy counts the bytes read and written."""
     import torch
     from paper_1305_3625_amd import binding
     src = torch.zeros(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     out = {}
     for kind, name, mult in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
-        best = None
+        best, sweep = None, {}
         for nt in (False, True):
-            for blocks in (1024, 2048, 4096, 8192):
+            for blocks in (1024, 2048, 4096, 8192, 16384):
                 ms = binding.stream_probe(kind, dst, src, nbytes, blocks, reps=10, nontemporal=nt)
                 gbps = mult * nbytes / (ms * 1e-3) / 1e9
+                sweep[f"{'nt' if nt else 'plain'}/{blocks}"] = round(gbps, 1)
                 if best is None or gbps > best[0]:
                     best = (gbps, nt, blocks)
-        out[name] = dict(GBps=round(best[0], 1), nontemporal=best[1], blocks=best[2])
+        out[name] = dict(GBps=round(best[0], 1), nontemporal=best[1], blocks=best[2], sweep=sweep)
     del src, dst
     torch.cuda.empty_cache()
     return out
