@@ -231,6 +231,7 @@ def scenario_queue_cap_and_maxit(f):
     """A queue of two: a burst meets EAGAIN; requests whose maxit is below
     their iteration count end FFTCG_ENOCONV with the last iterate, the others
     are unaffected."""
+    f.lib.fftcg_fake_set_event_delay(2000)  # chunks complete slowly: a burst fills the queue
     plan = f.plan(8, 1)
     srv = f.server(max_slots=1, queue_cap=2)
     rng = np.random.default_rng([9, 0])
@@ -256,6 +257,7 @@ def scenario_queue_cap_and_maxit(f):
             assert st == OK and np.array_equal(x, 0.5 * b)
     f.lib.fftcg_server_destroy(srv)
     f.lib.fftcg_fake_plan_free(plan)
+    f.lib.fftcg_fake_set_event_delay(0)
 
 
 def scenario_sequences(f):
@@ -307,7 +309,7 @@ def scenario_shutdown(f):
     """Shutdown with work queued and running: every request ends OK or
     FFTCG_ECANCELED, the counts agree, later submissions are refused, and
     the plans are free again."""
-    f.lib.fftcg_fake_set_event_delay(50)  # chunks complete slowly
+    f.lib.fftcg_fake_set_event_delay(2000)  # chunks complete slowly
     plan = f.plan(32, 0)
     srv = f.server(max_slots=4)
     rng = np.random.default_rng([11, 0])
