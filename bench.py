@@ -361,8 +361,9 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10, literal=False, full=True, 
     out = dict(requests=n_requests, sizes="L" if literal else "M", grids_M=grid,
                arrival_rate_per_s=round(n_requests / float(arrivals[-1]), 1), budget_bytes=budget,
                served_mixed=_round(served))
+    out["served_mixed_warm"] = _round(run_served(warm_n=min(len(reqs), 500))[0])
+    progress(f"serving: warm server p50 {out['served_mixed_warm']['p50_ms']:.2f} ms")
     if full:
-        out["served_mixed_warm"] = _round(run_served(warm_n=min(len(reqs), 500))[0])
         out["closed_loop_mixed"] = {lab: _round(d) for lab, d in run_closed_loop().items()}
         out["tight_budget_64MiB_first500"] = _round(run_served(budget=64 << 20, n=min(len(reqs), 500))[0])
     nb = len(reqs) if fp64_requests is None else min(len(reqs), fp64_requests)

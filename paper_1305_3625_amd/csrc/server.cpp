@@ -128,6 +128,10 @@ struct fftcg_server_s {
     std::mutex pin_mu;
     std::multimap<size_t, void*> pin_free;
     size_t pin_cached = 0;  // bytes idle in pin_free
+    // pageable input buffers kept for reuse (a fresh one page-faults on
+    // every first touch while the submission copies into it)
+    std::multimap<size_t, void*> page_free;
+    size_t page_cached = 0;
     size_t pin_inputs = 0;  // pinned input staging handed out
     size_t pin_input_cap = 0;  // a quarter of the device budget, in [1 MiB, 1 GiB]
 };
@@ -528,10 +532,19 @@ void scheduler(fftcg_server_s* srv) {
     }
 }
 
-bool all_finite(const double* a, size_t n) {
-    for (size_t i = 0; i < n; ++i)
-        if (!isfinite(a[i])) return false;
-    return true;
+enum CopyCheck { kFinite, kNonNegative, kPositive };
+
+// dst = src (n doubles), and whether every value is finite (and >= 0, or
+// > 0); the test accumulates without branches so the loop streams.
+bool copy_checked(double* __restrict__ dst, const double* __restrict__ src, size_t n, CopyCheck kind) {
+    bool ok = true;
+    for (size_t i = 0; i < n; ++i) {
+        const double v = src[i];
+        dst[i] = v;
+        const bool fin = v - v == 0.0;  // false for inf and nan
+        ok &= kind == kFinite ? fin : (kind == kNonNegative ? (fin && v >= 0.0) : (fin && v > 0.0));
+    }
+    return ok;
 }
 
 constexpr size_t kPinCacheBytes = size_t(2) << 30;  // idle pinned buffers kept
@@ -554,6 +567,13 @@ void* pin_get(fftcg_server_s* srv, size_t bytes, bool input, bool* pinned) {
         }
         if (input && srv->pin_inputs + bytes > srv->pin_input_cap) {
             *pinned = false;
+            auto pg = srv->page_free.find(bytes);
+            if (pg != srv->page_free.end()) {
+                void* p = pg->second;
+                srv->page_free.erase(pg);
+                srv->page_cached -= bytes;
+                return p;
+            }
             return malloc(bytes);
         }
         if (input) srv->pin_inputs += bytes;
@@ -572,6 +592,14 @@ void* pin_get(fftcg_server_s* srv, size_t bytes, bool input, bool* pinned) {
 void pin_put(fftcg_server_s* srv, void* p, size_t bytes, bool input, bool pinned) {
     if (!p) return;
     if (!pinned) {
+        {
+            std::lock_guard<std::mutex> lk(srv->pin_mu);
+            if (srv->page_cached + bytes <= kPinCacheBytes) {
+                srv->page_free.emplace(bytes, p);
+                srv->page_cached += bytes;
+                return;
+            }
+        }
         free(p);
         return;
     }
@@ -627,12 +655,6 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
     if (!plan->ops) return FFTCG_EINVAL;
     if (slot_footprint(plan) > srv->opts.memory_budget) return FFTCG_ENOMEM;
     const size_t n = (size_t)plan->L * plan->L;
-    for (size_t i = 0; i < n; ++i)
-        if (!(d[i] >= 0.0) || !isfinite(d[i])) return FFTCG_EINVAL;
-    if (!all_finite(b, n) || (x0 && !all_finite(x0, n))) return FFTCG_EINVAL;
-    if (t)
-        for (size_t i = 0; i < n; ++i)
-            if (!(t[i] > 0.0) || !isfinite(t[i])) return FFTCG_EINVAL;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->shut) return FFTCG_ECANCELED;
@@ -658,10 +680,15 @@ static int submit_common(fftcg_server_t srv, fftcg_plan_t plan, int precision, c
         free_request_buffers(srv, q.get());
         return FFTCG_ENOMEM;
     }
-    memcpy(q->pin_in, d, n * 8);
-    memcpy(q->pin_in + n, b, n * 8);
-    if (x0) memcpy(q->pin_in + 2 * n, x0, n * 8);
-    if (t) memcpy(q->pin_in + (x0 ? 3 : 2) * n, t, n * 8);
+    // inputs are checked while they are copied: one pass over the caller's
+    // memory (the copy dominates a large request's submission)
+    const bool valid = copy_checked(q->pin_in, d, n, kNonNegative) && copy_checked(q->pin_in + n, b, n, kFinite) &&
+                       (!x0 || copy_checked(q->pin_in + 2 * n, x0, n, kFinite)) &&
+                       (!t || copy_checked(q->pin_in + (x0 ? 3 : 2) * n, t, n, kPositive));
+    if (!valid) {
+        free_request_buffers(srv, q.get());
+        return FFTCG_EINVAL;
+    }
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->shut || srv->queued >= srv->opts.queue_cap) {
         free_request_buffers(srv, q.get());
@@ -839,6 +866,7 @@ extern "C" int fftcg_server_destroy(fftcg_server_t srv) try {
         free_request_buffers(srv, q);
     }
     for (auto& kv : srv->pin_free) (void)hipHostFree(kv.second);
+    for (auto& kv : srv->page_free) free(kv.second);
     delete srv;
     return FFTCG_OK;
 } FFTCG_ABI_CATCH

@@ -260,6 +260,35 @@ def scenario_queue_cap_and_maxit(f):
     f.lib.fftcg_fake_set_event_delay(0)
 
 
+def scenario_invalid_inputs(f):
+    """Non-finite or out-of-range inputs are refused at submission (checked
+    while they are copied), and nothing is queued for them."""
+    plan = f.plan(8, 1)
+    srv = f.server()
+    rng = np.random.default_rng([12, 0])
+    d, b = request(rng, 8)
+    for bad_d, bad_b in [(-1.0, None), (np.inf, None), (None, np.nan), (None, -np.inf)]:
+        dd, bb = d.copy(), b.copy()
+        if bad_d is not None:
+            dd[3, 5] = bad_d
+        if bad_b is not None:
+            bb[7, 7] = bad_b
+        assert f.submit(srv, plan, dd, bb)[0] == EINVAL
+    t = rng.uniform(0.1, 1.0, (8, 8))
+    t[0, 0] = 0.0
+    tk = U64()
+    assert f.lib.fftcg_submit_sequence(srv, plan, 1, d.ctypes.data_as(P), b.ctypes.data_as(P),
+                                       t.ctypes.data_as(P), 1e-8, 100, 4, ctypes.byref(tk)) == EINVAL
+    st, tk = f.submit(srv, plan, d, b)  # a valid one still goes through
+    assert st == OK
+    res = wait_all(f, srv, {tk: 8})
+    assert res[tk][0] == OK and np.array_equal(res[tk][1], 0.5 * b)
+    s = f.stats(srv)
+    assert s.submitted == 1 and s.completed == 1
+    f.lib.fftcg_server_destroy(srv)
+    f.lib.fftcg_fake_plan_free(plan)
+
+
 def scenario_sequences(f):
     """Load-stepped sequences: the breaks follow the rule on each step's
     solution, every step's bound and iteration count is reported."""
@@ -349,7 +378,8 @@ def scenario_graphs(f):
     assert counts[0] < counts[-1] / 2, counts
 
 
-ALL = [scenario_mix_two_clients, scenario_budget, scenario_queue_cap_and_maxit, scenario_sequences,
+ALL = [scenario_mix_two_clients, scenario_budget, scenario_queue_cap_and_maxit, scenario_invalid_inputs,
+       scenario_sequences,
        scenario_shutdown, scenario_graphs]
 
 if __name__ == "__main__":
