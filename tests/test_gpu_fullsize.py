@@ -127,13 +127,13 @@ def _wait(srv, tickets, L, timeout=300.0):
     return out
 
 
-@pytest.mark.parametrize("M", [512, 1024])
+@pytest.mark.parametrize("M", [512, 1024, 2048])  # 2048: the largest class when the drawn sizes are read as L
 def test_served_multipass_vs_oracle(M):
     L = M // 2
     gh = spectrum(M, 1e-3)
     plan = binding.Plan(L, 1, gh)
     srv = binding.Server(memory_budget=4 << 30)
-    reqs = [c4_request(5000 + 10 * M + k, M) for k in range(4)]
+    reqs = [c4_request(5000 + 10 * M + k, M) for k in range(4 if M < 2048 else 2)]
     banner("served-multipass", M, len(reqs))
     tks = []
     for r in reqs:
