@@ -158,6 +158,38 @@ int fftcg_plan_set_precond(fftcg_plan_t plan, int kind);
  * concurrently with solves on the same plan.                               */
 int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, double tau);
 
+/* fftcg_plan_set_grid_sync -- how the multi-pass engine ends a CG iteration
+ * in fftcg_solve and fftcg_fracture (Sec. 3, the r update of Listing 2).
+ *   mode 1 (default): where the device allows it, the update r <- r - alpha q
+ *          runs inside the row-inverse pass: each workgroup keeps its q in
+ *          registers, all workgroups meet at a grid-wide barrier (the launch
+ *          is cooperative) once their p.q partials are stored, and then
+ *          update their own rows.  q never reaches memory and one kernel per
+ *          iteration is saved.  FP32 working precision (FFTCG_MIXED) without
+ *          a preconditioner, on grids whose row-inverse pass is resident as
+ *          a whole (fftcg_plan_get_grid_sync reports where).
+ *   mode 0: the separate update kernel (as server classes always use).
+ *   mode 2: as mode 1 with the barrier's wait limit at zero, so that
+ *          workgroups give up at once; for tests of the fallback below.
+ * A barrier that is not met within its wait limit (100 ms; another stream's
+ * work can hold part of the device) abandons the solve, which is then
+ * repeated from its start with mode 0 semantics; the plan keeps the separate
+ * kernel from then on, until this call sets a mode again.  The result is
+ * the same either way (up to the rounding of the r.r partial sums).
+ * FFTCG_EINVAL for a NULL plan or another mode.  Not to be called
+ * concurrently with solves on the same plan.                               */
+int fftcg_plan_set_grid_sync(fftcg_plan_t plan, int mode);
+
+#define FFTCG_GRID_UNSUPPORTED 0 /* not on this grid, device or precision   */
+#define FFTCG_GRID_OFF         1 /* supported, mode 0                       */
+#define FFTCG_GRID_ON          2 /* supported and used by later solves      */
+#define FFTCG_GRID_FELL_BACK   3 /* a barrier gave up; separate kernel used */
+
+/* fftcg_plan_get_grid_sync -- *state = one of FFTCG_GRID_* for solves in
+ * `precision` on this plan.  FFTCG_EINVAL for a NULL argument or another
+ * precision.                                                               */
+int fftcg_plan_get_grid_sync(fftcg_plan_t plan, int precision, int* state);
+
 /* Reports L, M, padded, and the plan's device bytes (any pointer may be NULL). */
 int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, size_t* device_bytes);
 

@@ -22,6 +22,7 @@ EAGAIN, EDEVICE, ENOTFOUND, ECANCELED = -6, -7, -8, -9
 FP64, MIXED = 0, 1
 ENGINE_AUTO, ENGINE_MULTIPASS, ENGINE_FUSED = 0, 1, 2
 PRECOND_NONE, PRECOND_CIRCULANT = 0, 1
+GRID_UNSUPPORTED, GRID_OFF, GRID_ON, GRID_FELL_BACK = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "ENOCONV",
                 -5: "EBREAKDOWN", -6: "EAGAIN", -7: "EDEVICE", -8: "ENOTFOUND", -9: "ECANCELED"}
@@ -29,7 +30,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD"
 # every symbol include/fftcg.h declares
 EXPORTS = [
     "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond",
-    "fftcg_plan_set_error_target", "fftcg_plan_info",
+    "fftcg_plan_set_error_target", "fftcg_plan_set_grid_sync", "fftcg_plan_get_grid_sync", "fftcg_plan_info",
     "fftcg_apply", "fftcg_profile_apply", "fftcg_stream_probe", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_shutdown",
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH):
         "fftcg_plan_set_engine": (I, [P, I]),
         "fftcg_plan_set_precond": (I, [P, I]),
         "fftcg_plan_set_error_target": (I, [P, I, D]),
+        "fftcg_plan_set_grid_sync": (I, [P, I]),
+        "fftcg_plan_get_grid_sync": (I, [P, I, ctypes.POINTER(I)]),
         "fftcg_plan_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                 ctypes.POINTER(S)]),
         "fftcg_apply": (I, [P, I, P, P, P, P]),
@@ -214,6 +217,21 @@ class Plan:
         st = load().fftcg_plan_set_error_target(self.h, int(precision), float(tau))
         if st != OK:
             raise FftcgError(st, "fftcg_plan_set_error_target")
+
+    def set_grid_sync(self, mode: int):
+        """Update folded into the row-inverse pass behind a grid barrier:
+        1 on (default), 0 off, 2 on with a zero wait limit (fallback tests)."""
+        st = load().fftcg_plan_set_grid_sync(self.h, int(mode))
+        if st != OK:
+            raise FftcgError(st, "fftcg_plan_set_grid_sync")
+
+    def grid_sync(self, precision: int) -> int:
+        """One of GRID_UNSUPPORTED, GRID_OFF, GRID_ON, GRID_FELL_BACK."""
+        v = ctypes.c_int()
+        st = load().fftcg_plan_get_grid_sync(self.h, int(precision), ctypes.byref(v))
+        if st != OK:
+            raise FftcgError(st, "fftcg_plan_get_grid_sync")
+        return v.value
 
     def info(self):
         L, M, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -42,6 +42,16 @@ struct EngineOps {
     void (*check0)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride, hipStream_t s);
     void (*check0_pcg)(int prec, const PlanTabs& t, const SlotDesc* slots, int nslots, int stride,
                        hipStream_t s);
+    // one CG iteration of a single slot with the update folded into the
+    // row-inverse pass behind a grid-wide barrier (row_fwd, col, row_inv);
+    // token: unique per launch on the slot's partial-sum buffer.  Returns
+    // false (and runs the separate kernels) where grid_capable is false.
+    bool (*iter_grid)(int prec, const PlanTabs& t, const SlotDesc* slot, int stride, unsigned long long token,
+                      hipStream_t s);
+    // whether iter_grid applies on the current device: FP32 working
+    // precision, the whole row-inverse grid resident at once, and no more
+    // r.r partials per pass than the update kernel writes
+    bool (*grid_capable)(int prec);
 };
 
 const EngineOps* find_engine(int M, int pad);

@@ -98,6 +98,46 @@ void iter_t(const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, h
                        G<W>::ROW_BLOCKS, stride);
 }
 
+void iter_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s);
+
+// The same iteration for one slot with the update inside the row-inverse
+// pass (EpiCGU): the row-forward pass then reduces that pass's RB r.r
+// partials.  RB <= g4_blocks() (grid_capable_fn), so after an FP64 check,
+// which writes g4_blocks() of them (|r|^2 first, zeros after), the first RB
+// still hold the whole sum.
+bool iter_grid_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long token,
+                  hipStream_t s) {
+    if (prec == 0 || G<float>::ROW_BLOCKS > g4_blocks()) {
+        iter_fn(prec, pt, slot, 1, stride, s);
+        return false;
+    }
+    using W = float;
+    constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS, RB = G<W>::ROW_BLOCKS;
+    const ByPtr sp{slot};
+    const Tab<W> tab = tab_of<W>(pt);
+    hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProCG<W, W, RT>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, RB,
+                       stride);
+    hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
+    hipLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, token);
+    return true;
+}
+
+bool grid_capable_fn(int prec) {
+    using W = float;
+    constexpr int RT = G<W>::ROW_THREADS, RB = G<W>::ROW_BLOCKS;
+    if (prec == 0 || RB > g4_blocks()) return false;
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return false;
+    const auto kern = k_row_inv_upd<W, M, PAD, ByPtr, RT>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), RT, 0) !=
+        hipSuccess)
+        return false;
+    return (long)per_cu * cus >= RB;
+}
+
 void iter_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
     if (prec == 0)
         iter_t<double, double>(pt, slots, nslots, stride, s);
@@ -242,7 +282,9 @@ const EngineOps kOps = {M,
                         &iter_pcg_fn,
                         &check_pcg_fn,
                         &check0_fn,
-                        &check0_pcg_fn};
+                        &check0_pcg_fn,
+                        &iter_grid_fn,
+                        &grid_capable_fn};
 
 }  // namespace
 

@@ -261,6 +261,10 @@ extern "C" int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftc
     (void)hipGetDevice(&p->device);
     p->ops = find_engine(M, padded);
     p->stride = plan_stride(p->ops, L);
+    if (p->ops) {
+        p->grid_cap[0] = p->ops->grid_capable(FFTCG_FP64);
+        p->grid_cap[1] = p->ops->grid_capable(FFTCG_MIXED);
+    }
     // quarter spectrum (host copy, FP64) for the fused engine
     p->quarter.resize((size_t)(M / 2 + 1) * (M / 2 + 1));
     for (int m = 0; m <= M / 2; ++m)
@@ -364,6 +368,29 @@ extern "C" int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, dou
     if (plan->refs.load() > 0) return FFTCG_EINVAL;  // requests in a server use it
     std::lock_guard<std::mutex> lk(plan->mu);
     plan->tau_fixed[precision == FFTCG_MIXED ? 1 : 0] = tau;
+    return FFTCG_OK;
+} FFTCG_ABI_CATCH
+
+extern "C" int fftcg_plan_set_grid_sync(fftcg_plan_t plan, int mode) try {
+    if (!plan) return FFTCG_EINVAL;
+    if (mode < 0 || mode > 2) return FFTCG_EINVAL;
+    std::lock_guard<std::mutex> lk(plan->mu);
+    plan->grid_mode = mode;
+    plan->grid_broken.store(0);
+    return FFTCG_OK;
+} FFTCG_ABI_CATCH
+
+extern "C" int fftcg_plan_get_grid_sync(fftcg_plan_t plan, int precision, int* state) try {
+    if (!plan || !state) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    if (!plan->ops || !plan->grid_cap[precision == FFTCG_MIXED ? 1 : 0])
+        *state = FFTCG_GRID_UNSUPPORTED;
+    else if (plan->grid_mode == 0)
+        *state = FFTCG_GRID_OFF;
+    else if (plan->grid_broken.load())
+        *state = FFTCG_GRID_FELL_BACK;
+    else
+        *state = FFTCG_GRID_ON;
     return FFTCG_OK;
 } FFTCG_ABI_CATCH
 
@@ -601,11 +628,49 @@ struct ChunkPlanner {
     }
 };
 
+// Wait limit of the grid-wide barrier (ticks of the 100 MHz constant clock):
+// 100 ms, far beyond the few microseconds between the first and the last
+// workgroup of a resident grid.
+constexpr long long kGridWaitTicks = 10000000;
+
+static int solve_multipass_once(fftcg_plan_t plan, Workspace* w, int precision, const double* d, const double* b,
+                                const double* x0, double tol, int maxit, double* x, fftcg_info* info,
+                                hipStream_t s, const uint8_t* mask, bool grid);
+
 static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, const double* b, const double* x0,
                            double tol, int maxit, double* x, fftcg_info* info, hipStream_t s,
                            const uint8_t* mask = nullptr) {
     Workspace* w = plan_acquire(plan);
     if (!w) return FFTCG_ENOMEM;
+    const size_t n = (size_t)plan->L * plan->L;
+    bool grid = plan->grid_mode != 0 && !plan->grid_broken.load() && plan->grid_cap[precision == FFTCG_MIXED] &&
+                plan->precond == FFTCG_PRECOND_NONE;
+    int rc = FFTCG_OK;
+    // a warm start in place is kept in q, which the grid-synchronised path
+    // never writes, so that a solve abandoned at a barrier can be repeated
+    if (grid && x0 && x0 == x &&
+        hipMemcpyAsync(w->q, x, n * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        grid = false;
+    rc = solve_multipass_once(plan, w, precision, d, b, x0, tol, maxit, x, info, s, mask, grid);
+    if (rc == ST_EGRID) {
+        // the grid was not resident as a whole (other work on the device):
+        // the plan falls back to the separate update kernel, and the solve
+        // is repeated from its start
+        plan->grid_broken.store(1);
+        rc = FFTCG_OK;
+        if (x0 && x0 == x && hipMemcpyAsync(x, w->q, n * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            rc = FFTCG_EDEVICE;
+        if (rc == FFTCG_OK)
+            rc = solve_multipass_once(plan, w, precision, d, b, x0, tol, maxit, x, info, s, mask, false);
+        if (rc == ST_EGRID) rc = FFTCG_EDEVICE;
+    }
+    plan_release(plan, w);
+    return rc;
+}
+
+static int solve_multipass_once(fftcg_plan_t plan, Workspace* w, int precision, const double* d, const double* b,
+                                const double* x0, double tol, int maxit, double* x, fftcg_info* info,
+                                hipStream_t s, const uint8_t* mask, bool grid) {
     const EngineOps* ops = plan->ops;
     const size_t n = (size_t)plan->L * plan->L;
     int rc = FFTCG_OK;
@@ -613,6 +678,7 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
         fill_slot(w->h_slot, w, x, b, d);
         w->h_slot->mask = mask;
         init_state(w->h_state, plan, precision, tol, maxit, 50);
+        w->h_state->bar_limit = plan->grid_mode == 2 ? 0 : kGridWaitTicks;
         for (int i = 0; i < 4; ++i) w->h_status[i] = 0;
         if (hipMemcpyAsync(w->slot, w->h_slot, sizeof(SlotDesc), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(w->st, w->h_state, sizeof(SolveState), hipMemcpyHostToDevice, s) != hipSuccess) {
@@ -655,7 +721,12 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
         bool finished = false;
         while (!finished) {
             const int K = planner.next();
-            for (int k = 0; k < K; ++k) iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
+            for (int k = 0; k < K; ++k) {
+                if (grid)
+                    grid = ops->iter_grid(precision, plan->tabs, w->slot, plan->stride, ++w->grid_token, s);
+                else
+                    iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
+            }
             check(precision, plan->tabs, w->slot, 1, plan->stride, s);
             if (hipGetLastError() != hipSuccess || hipEventRecord(w->ev[c & 1], s) != hipSuccess) {
                 rc = FFTCG_EDEVICE;
@@ -695,9 +766,8 @@ static int solve_multipass(fftcg_plan_t plan, int precision, const double* d, co
             }
         }
         rc = st.status;
-        fill_info(info, st, ms);
+        if (rc != ST_EGRID) fill_info(info, st, ms);
     } while (0);
-    plan_release(plan, w);
     return rc;
 }
 

@@ -53,6 +53,9 @@ struct Workspace {
     int* h_ls = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // launches of the grid-synchronised update on this workspace's partial
+    // sums (each launch's barrier token is the next value)
+    unsigned long long grid_token = 0;
     int init(int L, int M, int stride);
     void release();
     ~Workspace();
@@ -100,6 +103,14 @@ struct fftcg_plan_s {
     void* f_tab64 = nullptr;  // per-plan constant tables of the fused engine
     void* f_tab32 = nullptr;
     size_t fused_bytes = 0;
+    // update folded into the row-inverse pass behind a grid-wide barrier
+    // (single solves, plain CG): mode 0 off, 1 on, 2 on with a zero wait
+    // limit (tests of the fallback); capability per precision, found at
+    // plan creation; set once a barrier gave up (the plan then keeps the
+    // separate update kernel until the mode is set again)
+    int grid_mode = 1;
+    bool grid_cap[2] = {false, false};
+    std::atomic<int> grid_broken{0};
     std::mutex mu;
     std::vector<fftcg::Workspace*> free_ws;
     std::vector<fftcg::Workspace*> all_ws;

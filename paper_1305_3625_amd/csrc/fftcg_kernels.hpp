@@ -697,7 +697,96 @@ struct EpiCG {
         st2<W>(q + idx, qv);
         acc[0] += (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
     }
+    // q of a pair without storing it (the grid-synchronised update below)
+    template <int L>
+    static __device__ __forceinline__ cx<W> outq(const SlotDesc& sd, int row, int col, W c0, W c1, const Pre& pr,
+                                                 double* acc) {
+        const cx<W> pv = pr.p, dv = pr.d;
+        cx<W> qv = mkc(dv.x * pv.x + c0, dv.y * pv.y + c1);
+        if (sd.mask) {
+            const Mask2 mk = mask2(sd, (size_t)row * L + col);
+            qv = mkc(qv.x * (W)mk.m0, qv.y * (W)mk.m1);
+        }
+        acc[0] += (double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y;
+        return qv;
+    }
 };
+
+// The CG epilogue with the residual update folded in (FP32 only): q = A p
+// never leaves registers.  After every workgroup has published its p.q
+// partial (a grid-wide barrier; the launch is cooperative, so the whole grid
+// is resident), each workgroup forms alpha = rho / (p.q) from all partials
+// in the same order and updates r <- r - alpha q on its own rows, with the
+// r.r partials of the next iteration.  It replaces the separate update
+// kernel: one pass over q fewer, and one kernel boundary fewer.
+template <typename W>
+struct EpiCGU : EpiCG<W> {
+    static_assert(sizeof(W) == 4, "the grid-synchronised update keeps FP32 q in registers");
+    static constexpr bool UPD = true;
+};
+template <class E, class = void>
+struct EpiUpd {
+    static constexpr bool value = false;
+};
+template <class E>
+struct EpiUpd<E, decltype((void)E::UPD)> {
+    static constexpr bool value = E::UPD;
+};
+
+// Grid-wide barrier without read-modify-write traffic on one address (1,024
+// atomic additions to one counter serialise where they are performed and
+// cost tens of microseconds).  Each launch carries a token that no other
+// launch on the same partial-sum buffer uses.  A workgroup arrives by
+// storing the token to its own word flags[b]; workgroup 0 waits until every
+// flag holds the token, then stores it to the release word *rel, which the
+// others wait for.  All of these are agent-scope atomics, performed where
+// every XCD sees them, and each step waits for the previous step's value, so
+// no cache-wide fence is needed (a release/acquire pair at agent scope
+// writes back and invalidates the L2 of every workgroup's XCD, which costs
+// more than the whole update).  Waits are bounded: after `limit` ticks of
+// the 100 MHz constant clock the workgroup gives up and false is returned (a
+// grid that is not resident as a whole cannot complete the barrier).
+// Called by every thread of the workgroup; returns the same value in all.
+template <int NT>
+__device__ inline bool grid_barrier(unsigned long long* flags, unsigned long long* rel, unsigned long long token,
+                                    long long limit) {
+    __shared__ int s_ok;
+    const int tid = threadIdx.x;
+    const unsigned int nb = gridDim.x;
+    if (tid == 0) __hip_atomic_store(flags + blockIdx.x, token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    int ok = 1;
+    if (blockIdx.x == 0) {
+        for (;;) {
+            int mine = 1;
+            for (unsigned int i = tid; i < nb; i += NT)
+                mine &= __hip_atomic_load(flags + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == token;
+            const int expired = (long long)(__builtin_amdgcn_s_memrealtime() - t0) > limit;
+            // both decisions are taken by the whole workgroup
+            if (__syncthreads_and(mine)) break;
+            if (__syncthreads_or(expired)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok && tid == 0) __hip_atomic_store(rel, token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        if (tid == 0) {
+            while (__hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != token) {
+                if ((long long)(__builtin_amdgcn_s_memrealtime() - t0) > limit) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        ok = s_ok;
+    }
+    return ok != 0;
+}
 
 // FP64 check: r64 = b - d x - C x; r (working precision) <- r64; partials of
 // |r64|^2, |x|^2, |b|^2, |r|^2, min d, the count of invalid inputs and
@@ -970,8 +1059,11 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
         }
 }
 
+// Body of the row-inverse pass; token: the grid-wide barrier's arrival
+// token of this launch (epilogues with the folded update only).
 template <typename T, int M, int PAD, class Epi, class Slot, int NT>
-__global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int stride) {
+__device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot, int stride,
+                                             unsigned long long token) {
     using G = Geo<T, M, PAD>;
     constexpr int N = G::N, E = G::ER, P = G::PR, RPW = G::RPW, L = G::L, TT = G::TT;
     constexpr int WORDS = G::ROW_WORDS;
@@ -1059,18 +1151,33 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
 #pragma unroll
     for (int a = 0; a < (Epi::NACC > 0 ? Epi::NACC : 1); ++a) acc[a] = 0.0;
     if constexpr (Epi::NACC > 4) acc[4] = 1.0e300;
+    constexpr bool UPD = EpiUpd<Epi>::value;
+    constexpr int NO = (E / RL) * RK;  // outputs (pairs) of this thread
+    cx<T> qk[UPD ? NO : 1], rk[UPD ? NO : 1];
 #pragma unroll
     for (int u = 0; u < E / RL; ++u)
 #pragma unroll
         for (int r = 0; r < RK; ++r) {
             const int n = (j + u * P) + r * (N / RL);
-            if constexpr (Epi::PREF) {
+            if constexpr (UPD) {
+                qk[u * RK + r] = Epi::template outq<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y,
+                                                       pre[u * RK + r], acc);
+            } else if constexpr (Epi::PREF) {
                 Epi::template out2p<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, pre[u * RK + r], acc);
             } else {
                 Epi::template out2<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, acc);
             }
         }
-    if constexpr (Epi::NACC > 0) {
+    if constexpr (UPD) {
+        // r of the same pairs, requested before the reduction and the barrier
+        // so that its latency hides behind them
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RK; ++r)
+                rk[u * RK + r] = ld2<T>(reinterpret_cast<const T*>(sd.r) + (size_t)row * L + 2 * ((j + u * P) + r * (N / RL)));
+    }
+    if constexpr (Epi::NACC > 0 && !UPD) {
         double* part = sd.part;
         if constexpr (Epi::NACC == 1) {
             const double s = block_sum<NT>(acc[0], red);
@@ -1091,6 +1198,80 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
             }
         }
     }
+    if constexpr (UPD) {
+        SolveState* st = sd.st;
+        auto* pq_bits = reinterpret_cast<unsigned long long*>(sd.part + PS_PQ * stride);
+        auto* bar_rel = reinterpret_cast<unsigned long long*>(sd.part + PS_BARREL * stride);
+        const double s_pq = block_sum<NT>(acc[0], red);
+        if (tid == 0) {
+            // the partial is exchanged atomically and its completion awaited
+            // (s_waitcnt 0) before the arrival is stored
+            (void)__hip_atomic_exchange(pq_bits + blockIdx.x, __builtin_bit_cast(unsigned long long, s_pq),
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        const bool ok = grid_barrier<NT>(reinterpret_cast<unsigned long long*>(sd.part + PS_BAR * stride), bar_rel,
+                                         token, st->bar_limit);
+        if (!ok) {
+            // the grid was not resident as a whole: the solve is abandoned
+            // and the host repeats it with the separate update kernel
+            if (tid == 0) {
+                __hip_atomic_store(&st->status, ST_EGRID, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                publish_status(sd, 1, ST_EGRID, st->gen, st->iters, st->last_check_iter);
+            }
+            return;
+        }
+        // every partial, in the order of the update kernel's reduction
+        double spq = 0.0;
+        for (int i = tid; i < (int)gridDim.x; i += NT)
+            spq += __builtin_bit_cast(double, __hip_atomic_load(pq_bits + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const double pq = block_sum<NT>(spq, red);
+        const double rho = st->rho_cur;
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
+            if (blockIdx.x == 0 && tid == 0) {
+                st->status = ST_EBREAKDOWN;
+                st->done = 1;
+                publish_status(sd, 1, ST_EBREAKDOWN, st->gen, st->iters, st->last_check_iter);
+            }
+            return;
+        }
+        const double alpha = rho / pq;
+        if (blockIdx.x == 0 && tid == 0) {
+            st->alpha = alpha;
+            st->rho_prev = rho;
+            st->iters += 1;
+            st->restart = 0;
+        }
+        const T a = (T)alpha;
+        double rr = 0.0;
+#pragma unroll
+        for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+            for (int r = 0; r < RK; ++r) {
+                cx<T> rv = rk[u * RK + r];
+                const cx<T> qv = qk[u * RK + r];
+                rv.x -= a * qv.x;
+                rv.y -= a * qv.y;
+                st2<T>(reinterpret_cast<T*>(sd.r) + (size_t)row * L + 2 * ((j + u * P) + r * (N / RL)), rv);
+                rr += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            }
+        const double srr = block_sum<NT>(rr, red);
+        if (tid == 0) sd.part[PS_RR * stride + blockIdx.x] = srr;
+    }
+}
+
+template <typename T, int M, int PAD, class Epi, class Slot, int NT>
+__global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int stride) {
+    row_inv_body<T, M, PAD, Epi, Slot, NT>(tab, slot, stride, 0);
+}
+
+// The CG row-inverse pass with the residual update folded in (EpiCGU).
+// token: unique per launch (the host counts launches per workspace), so
+// arrival words left by an abandoned launch can never match a later one.
+template <typename T, int M, int PAD, class Slot, int NT>
+__global__ void __launch_bounds__(NT) k_row_inv_upd(Tab<T> tab, Slot slot, int stride, unsigned long long token) {
+    row_inv_body<T, M, PAD, EpiCGU<T>, Slot, NT>(tab, slot, stride, token);
 }
 
 // r <- r - alpha q, partial r . r.  alpha = rho / (p . q) from the partials

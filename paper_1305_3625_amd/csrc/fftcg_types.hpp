@@ -48,7 +48,12 @@ struct SolveState {
     int gen;             // generation of this solve (published with the status)
     int pcg;             // 1: Fourier-space (circulant) preconditioned CG
     int need_pre;        // 1: z = P^{-1} r is due after a check (check finaliser)
+    long long bar_limit;  // wait limit of the update's grid-wide barrier, ticks of the 100 MHz clock
 };
+
+// Internal solve status (never returned to callers): a grid-wide barrier
+// gave up waiting, so the host repeats the solve without it.
+constexpr int ST_EGRID = -100;
 
 // Per-slot descriptor (device memory).
 struct SlotDesc {
@@ -85,7 +90,9 @@ enum PartSet {
     PS_CHK_DIFF = 8,  // |r64 - r_recursive|^2: drift of the recursive residual
     PS_RZ = 9,        // r . z per block of the preconditioner's row-inverse pass
     PS_CHK_DSUM = 10, // sum of d (for its mean)
-    NPART_SETS = 11
+    PS_BAR = 11,      // grid-wide barrier: arrival token per block (64-bit words)
+    PS_BARREL = 12,   // [0] the barrier's release word (64 bits)
+    NPART_SETS = 13
 };
 
 }  // namespace fftcg

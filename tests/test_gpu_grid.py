@@ -1,0 +1,173 @@
+"""The CG update folded into the row-inverse pass behind a grid-wide barrier
+(fftcg_plan_set_grid_sync), against the separate update kernel and the
+oracle.
+
+Sec. 3 (the update r <- r - alpha q of the CG iteration, Listing 2): the
+folded form computes the same alpha from the same p.q partials in the same
+order and the same r update; only the r.r partial sums are grouped
+differently, so solutions agree to within the solves' tolerance, not bitwise.
+
+* which grids and precisions take it (FP32 working precision only);
+* full-size C3 instance, folded and separate, both against the oracle's
+  stored solution samples;
+* L = 256 against the oracle's solution run to stagnation;
+* the fallback: a barrier that gives up (wait limit forced to zero from the
+  host, every workgroup still exits) makes the host repeat the solve with the
+  separate kernel; the result is bitwise the separate kernel's, also for a
+  warm start given in place (x0 == x);
+* the masked operator of the fracture driver (Sec. 2) through the folded
+  path at L = 512, breaks replayed by the oracle.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1305_3625_amd import binding
+from workloads import spectrum, c3_instance, padded_instance, fracture_instance
+from oracle import reference_solve, fracture_sequence
+from gpu_util import dev, host, relerr, banner
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _solve(plan, inst, mode, x0=None, tol=1e-8):
+    import torch
+    L = inst["L"]
+    plan.set_grid_sync(mode)
+    x = torch.zeros((L, L), dtype=torch.float64, device="cuda") if x0 is None else x0
+    info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, x0=None if x0 is None else x, tol=tol,
+                      precision=binding.MIXED, raise_on_error=False)
+    return host(x), info
+
+
+def test_grid_sync_states():
+    L = 2048
+    plan = binding.Plan(L, 1, spectrum(2 * L, 1e-4))
+    banner("grid-states", L)
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    assert plan.grid_sync(binding.FP64) == binding.GRID_UNSUPPORTED
+    plan.set_grid_sync(0)
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_OFF
+    plan.set_grid_sync(1)
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    for bad in (-1, 3):
+        with pytest.raises(binding.FftcgError):
+            plan.set_grid_sync(bad)
+    plan.close()
+
+
+@pytest.mark.parametrize("s", [0])
+def test_grid_full_size_against_oracle_samples(s):
+    with open(os.path.join(GOLD, f"padded_L2048_seed{s}_samples.json")) as fh:
+        g = json.load(fh)
+    inst = c3_instance(s)
+    plan = binding.Plan(2048, 1, inst["ghat"])
+    banner("grid-L2048", s)
+    pos = np.array(g["pos"])
+    xs = {}
+    for mode in (1, 0):
+        x, info = _solve(plan, inst, mode)
+        assert info["status"] == binding.OK and info["error_bound"] <= 1e-8, (mode, info)
+        gap = np.max(np.abs(x.ravel()[pos] - np.array(g["x"])))
+        print(f"mode {mode}: iters {info['iterations']} bound {info['error_bound']:.3e} "
+              f"max sampled gap {gap / g['xnorm']:.3e}")
+        assert gap <= (1e-8 + g["bound"]) * g["xnorm"], (mode, gap)
+        xs[mode] = (x, info)
+        # mode 1 ran folded throughout (no barrier gave up)
+        assert plan.grid_sync(binding.MIXED) == (binding.GRID_ON if mode == 1 else binding.GRID_OFF)
+    assert abs(xs[1][1]["iterations"] - xs[0][1]["iterations"]) <= 2
+    assert relerr(xs[1][0], xs[0][0]) <= 2e-8
+    plan.close()
+
+
+def test_grid_L256_against_oracle():
+    L = 256
+    inst = padded_instance(L, [3, 7], eps=1e-4, normal_b=True)
+    xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 1)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("grid-L256", L)
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    for mode in (1, 0):
+        x, info = _solve(plan, inst, mode)
+        err = relerr(x, xr)
+        print(f"mode {mode}: iters {info['iterations']} error {err:.3e} (oracle bound {rinfo['bound']:.1e})")
+        assert info["status"] == binding.OK
+        assert err <= 1e-8 + rinfo["bound"]
+    plan.close()
+
+
+def test_grid_fallback_repeats_solve():
+    L = 512
+    inst = padded_instance(L, [3, 8], eps=1e-4, normal_b=True)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("grid-fallback", L)
+    x0, info0 = _solve(plan, inst, 0)
+    x2, info2 = _solve(plan, inst, 2)
+    assert info2["status"] == binding.OK
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_FELL_BACK
+    # the repeated solve is the separate kernel's, bitwise
+    assert np.array_equal(x2, x0) and info2["iterations"] == info0["iterations"]
+    # setting a mode again takes the folded path up again
+    plan.set_grid_sync(1)
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    x1, info1 = _solve(plan, inst, 1)
+    assert info1["status"] == binding.OK and relerr(x1, x0) <= 2e-8
+    plan.close()
+
+
+def test_grid_fallback_warm_start_in_place():
+    """x0 == x: the abandoned attempt overwrote x, the repeat starts from
+    the caller's x0 again (kept aside while the folded path runs)."""
+    import torch
+    L = 512
+    inst = padded_instance(L, [3, 9], eps=1e-4, normal_b=True)
+    rng = np.random.default_rng([3, 9, 1])
+    w = rng.standard_normal((L, L)) * 0.1
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("grid-fallback-in-place", L)
+    xa = dev(w)
+    xa_h, info_a = _solve(plan, inst, 0, x0=xa)
+    xb = dev(w)
+    xb_h, info_b = _solve(plan, inst, 2, x0=xb)
+    assert info_a["status"] == binding.OK and info_b["status"] == binding.OK
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_FELL_BACK
+    assert np.array_equal(xa_h, xb_h) and info_a["iterations"] == info_b["iterations"]
+    torch.cuda.synchronize()
+    plan.close()
+
+
+def test_grid_fracture_masked_L512():
+    """The fracture driver's projected (masked) operator through the folded
+    update, plain CG in mixed precision; every break is a valid choice for
+    the oracle's replay and the forces match."""
+    import torch
+    L, steps, tol = 512, 6, 1e-8
+    inst = fracture_instance(0, L=L)
+    gh = spectrum(2 * L, 1e-3)
+    plan = binding.Plan(L, 1, gh)
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    f = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    banner("grid-fracture-L512", steps)
+    st, broken, dbreak, iters = plan.fracture(inst["k"], dev(inst["t"]), f, steps, tol=tol,
+                                              precision=binding.MIXED)
+    assert st == binding.OK
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    _, fo_dbreak, fo_f, ratios = fracture_sequence(gh, inst["k"], inst["t"], steps, 1, replay=broken)
+    t = inst["t"].ravel()
+    for s in range(steps):
+        rho = ratios[s].ravel()
+        k = int(np.argmax(rho))
+        j = int(broken[s])
+        assert np.isfinite(rho[j]), (s, j)
+        einf = 2 * tol * np.linalg.norm(np.where(np.isfinite(rho), rho * t, 0.0))
+        assert rho[j] >= rho[k] - einf * (1.0 / t[j] + 1.0 / t[k]), (s, j, k)
+    np.testing.assert_allclose(dbreak, fo_dbreak, rtol=50 * tol)
+    err = relerr(host(f), fo_f)
+    print(f"mean iters {iters.mean():.1f}, force error {err:.3e}")
+    assert err <= 10 * tol
+    plan.close()
