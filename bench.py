@@ -5,8 +5,9 @@ Workload: mixed-precision solves on the zero-padded 2048 x 2048 grid
 (M = 4096), kernel eps = 1e-4, d ~ U(0.5, 1.5) with 30% zeros, b ~ N(0, 1),
 error target 1e-8 (three seeded instances, cycled).  A step is one complete
 solve: initial FP64 residual, every CG iteration (row R2C, column
-FFT*ghat*IFFT, row C2R + epilogue, update) and every FP64 check, until the
-certified stop rule holds.  Inputs are resident in HBM before timing.
+FFT*ghat*IFFT, row C2R + epilogue with the residual update folded in behind
+a grid-wide barrier, where the device allows it) and every FP64 check, until
+the certified stop rule holds.  Inputs are resident in HBM before timing.
 
 Printed as one JSON line: solves/s, matvecs/s, FFT GFLOP/s, effective HBM
 GB/s, the roofline of the dominant kernel (the column pass, timed live with
@@ -42,7 +43,10 @@ def kernel_hash():
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
-    h.update(repr((build.CXXFLAGS, build.ENGINE_SIZES, build.ARCH)).encode())
+    # include directories name this checkout's path, which differs between
+    # machines: only the code-generation flags count
+    flags = [f for f in build.CXXFLAGS if not f.startswith("-I")]
+    h.update(repr((flags, build.ENGINE_SIZES, build.ARCH)).encode())
     return h.hexdigest()[:16]
 
 
@@ -54,9 +58,13 @@ def bytes_model(L, M):
     W = 8 * L * N                    # one sweep over the FP32 half spectrum
     col = 2 * W + spec               # column pass: read W, read ghat, write W
     it = (20 * n + W) + col + (W + 12 * n) + 12 * n   # row_fwd + col + row_inv + update
+    # single solves with the update folded into the row-inverse pass: it
+    # reads r and writes r instead of writing q, and the update pass is gone
+    it_folded = (20 * n + W) + col + (W + 16 * n)
     chk = (28 * n + 2 * W) + (4 * W + 2 * spec) + (2 * W + 32 * n)  # FP64 check passes
     apply = (8 * n + W) + col + (W + 24 * n)          # fftcg_apply, FP32 operator
-    return dict(col=col, iteration=it, check=chk, apply=apply, per_column=16 * L + 4 * (M // 2 + 1))
+    return dict(col=col, iteration=it, iteration_folded=it_folded, check=chk, apply=apply,
+                per_column=16 * L + 4 * (M // 2 + 1))
 
 
 def fft_flops_nominal(M):
@@ -176,6 +184,33 @@ def hbm_ceiling(nbytes=1 << 30):
                 if best is None or gbps > best[0]:
                     best = (gbps, nt, blocks)
         out[name] = dict(GBps=round(best[0], 1), nontemporal=best[1], blocks=best[2], sweep=sweep)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def stream_by_size(sizes_mib=(32, 64, 128, 256, 1024)):
+    """Best streaming rate (read-only, write-only, copy) against the buffer
+    size: below the 256 MB last-level (Infinity) cache the data of repeated
+    launches stays there, as the CG iteration's working set (about 134 MB in
+    mixed precision at L = 2048) does.  Copy moves `size` each way."""
+    import torch
+    from paper_1305_3625_amd import binding
+    big = max(sizes_mib) << 20
+    src = torch.zeros(big // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for mib in sizes_mib:
+        nbytes = mib << 20
+        row = {}
+        for kind, name, mult in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+            best = 0.0
+            for nt in (False, True):
+                for blocks in (8192, 16384):
+                    ms = binding.stream_probe(kind, dst, src, nbytes, blocks, reps=10, nontemporal=nt)
+                    best = max(best, mult * nbytes / (ms * 1e-3) / 1e9)
+            row[name] = round(best, 1)
+        out[f"{mib}MiB"] = row
     del src, dst
     torch.cuda.empty_cache()
     return out
@@ -648,7 +683,9 @@ def main(argv=None):
     checks = [inf["checks"] for inf in infos]
     matvecs = sum(iters) + sum(checks)
     bm = bytes_model(L, M)
-    bytes_total = sum(iters) * bm["iteration"] + sum(checks) * bm["check"]
+    grid_state = plan.grid_sync(binding.MIXED)
+    folded = grid_state == binding.GRID_ON
+    bytes_total = sum(iters) * bm["iteration_folded" if folded else "iteration"] + sum(checks) * bm["check"]
 
     # live per-pass timing of one product (HIP events on the launch stream)
     y = torch.empty((L, L), dtype=torch.float64, device="cuda")
@@ -681,6 +718,12 @@ def main(argv=None):
     del src, dst
     copy_gbps = max(ceiling["copy"]["GBps"], torch_copy_gbps)
     progress(f"HBM probes: {ceiling}")
+    by_size = stream_by_size()
+    # the column pass's working set (W both ways and the quarter spectrum,
+    # about 50 MB here) stays in the last-level cache between launches:
+    # its practical ceiling is the copy rate at that size
+    resident_copy = max(v["copy"] for k, v in by_size.items() if int(k[:-3]) <= 64)
+    progress(f"streaming by size: {by_size}")
 
     # the oracle's FP64 residual of each instance's GPU solution, turned into
     # a certified error bound
@@ -777,9 +820,14 @@ def main(argv=None):
             "copy_GBps": round(copy_gbps, 1),
             "frac_of_copy": round(achieved / copy_gbps, 4),
             "stream_probes": ceiling,
+            "stream_by_size": by_size,
+            "copy_GBps_cache_resident": round(resident_copy, 1),
+            "frac_of_copy_cache_resident": round(achieved / resident_copy, 4),
             "torch_copy_GBps": round(torch_copy_gbps, 1),
         },
         "cpu_baseline": cpu,
+        "update_folded": folded,
+        "grid_sync_state": grid_state,
         "iterations_mean": round(float(np.mean(iters)), 2),
         "checks_mean": round(float(np.mean(checks)), 2),
         "matvecs_per_s": round(matvecs / elapsed, 1),
