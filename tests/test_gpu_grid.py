@@ -171,3 +171,49 @@ def test_grid_fracture_masked_L512():
     print(f"mean iters {iters.mean():.1f}, force error {err:.3e}")
     assert err <= 10 * tol
     plan.close()
+
+
+def test_grid_repeatable():
+    """Two folded solves of the same system agree bitwise (alpha and the
+    r.r partials are summed in a fixed order; the barrier adds no order)."""
+    L = 1024
+    inst = padded_instance(L, [3, 10], eps=1e-4, normal_b=True)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("grid-repeatable", L)
+    xa, ia = _solve(plan, inst, 1)
+    xb, ib = _solve(plan, inst, 1)
+    assert ia["status"] == binding.OK and ib["status"] == binding.OK
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    assert np.array_equal(xa, xb) and ia["iterations"] == ib["iterations"]
+    plan.close()
+
+
+def test_grid_with_other_stream_busy():
+    """A solve while another stream keeps the device busy (FP32 matrix
+    products, about 0.2 s): whether the barrier completes or gives up and
+    the solve is repeated with the separate kernel, the result is the
+    separate kernel's to within the tolerance."""
+    import torch
+    L = 2048
+    inst = c3_instance(1)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("grid-busy-device", L)
+    x0, i0 = _solve(plan, inst, 0)
+    plan.set_grid_sync(1)
+    a = torch.randn(8192, 8192, device="cuda")
+    bm = torch.randn(8192, 8192, device="cuda")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for _ in range(20):
+            c = torch.mm(a, bm)
+    x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, tol=1e-8, precision=binding.MIXED, raise_on_error=False)
+    torch.cuda.synchronize()
+    state = plan.grid_sync(binding.MIXED)
+    print(f"state {state}, iters {info['iterations']} (separate {i0['iterations']}), "
+          f"bound {info['error_bound']:.3e}, checksum {float(c[0, 0]):.3e}")
+    assert info["status"] == binding.OK and info["error_bound"] <= 1e-8
+    assert state in (binding.GRID_ON, binding.GRID_FELL_BACK)
+    assert relerr(host(x), x0) <= 2e-8
+    plan.close()
