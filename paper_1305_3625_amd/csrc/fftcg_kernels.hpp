@@ -331,10 +331,17 @@ struct ProCG {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->rho_cur = rr;
         return true;
     }
-    // FP32: the pair's r, p and x correction are requested before the r.r
-    // reduction (fetch), so that the reduction's latency overlaps them; the
-    // arithmetic (combine) is the same either way
+    // FP32: the pair's r and p are requested before the r.r reduction
+    // (fetch), so that the reduction's latency overlaps them; the arithmetic
+    // (combine) is the same either way.  The pending x update (late) runs
+    // after the transform: its reads then overlap the W writes instead of
+    // lengthening the pass's first, read-only phase (p stays in registers
+    // until then, within the pass's register budget)
     static constexpr bool PREF = sizeof(W) == 4;
+#ifndef FFTCG_LATE_X
+#define FFTCG_LATE_X 1
+#endif
+    static constexpr bool LATE_X = PREF && FFTCG_LATE_X;
     struct Raw {
         cx<W> r, p;
         cx<XA> x;
@@ -348,7 +355,7 @@ struct ProCG {
         Raw w;
         w.r = ld2<W>(reinterpret_cast<const W*>(sd.r) + idx);
         w.p = ld2<W>(reinterpret_cast<const W*>(sd.p) + idx);
-        w.x = ld2<XA>(xacc(sd) + idx);
+        if constexpr (!LATE_X) w.x = ld2<XA>(xacc(sd) + idx);
         return w;
     }
     template <int L>
@@ -361,15 +368,27 @@ struct ProCG {
         } else {
             const cx<W> po = w.p;
             p2 = mkc(w.r.x + sh.beta * po.x, w.r.y + sh.beta * po.y);
-            if (sh.alpha != W(0)) {
-                cx<XA> xv = w.x;
-                xv.x += (XA)sh.alpha * (XA)po.x;
-                xv.y += (XA)sh.alpha * (XA)po.y;
-                st2<XA>(xacc(sd) + idx, xv);
+            if constexpr (!LATE_X) {
+                if (sh.alpha != W(0)) {
+                    cx<XA> xv = w.x;
+                    xv.x += (XA)sh.alpha * (XA)po.x;
+                    xv.y += (XA)sh.alpha * (XA)po.y;
+                    st2<XA>(xacc(sd) + idx, xv);
+                }
             }
         }
         st2<W>(reinterpret_cast<W*>(sd.p) + idx, p2);
         return p2;
+    }
+    // the pending x update of the pair, after the transform (LATE_X)
+    template <int L>
+    static __device__ __forceinline__ void late(const SlotDesc& sd, const Sh& sh, const Raw& w, int row, int col) {
+        if (sh.restart || sh.alpha == W(0)) return;
+        const size_t idx = (size_t)row * L + col;
+        cx<XA> xv = ld2<XA>(xacc(sd) + idx);
+        xv.x += (XA)sh.alpha * (XA)w.p.x;
+        xv.y += (XA)sh.alpha * (XA)w.p.y;
+        st2<XA>(xacc(sd) + idx, xv);
     }
     template <int L>
     static __device__ __forceinline__ cx<W> load2(const SlotDesc& sd, const Sh& sh, int row, int col, double*) {
@@ -862,6 +881,26 @@ struct EpiPre {
     }
 };
 
+// Whether a prologue defers part of its work until after the transform.
+template <class P, class = void>
+struct ProLate {
+    static constexpr bool value = false;
+};
+template <class P>
+struct ProLate<P, decltype((void)P::LATE_X)> {
+    static constexpr bool value = P::LATE_X;
+};
+
+// A prologue's fetched operands kept for its late part (int otherwise).
+template <class P, bool = ProLate<P>::value>
+struct LateRaw {
+    using type = int;
+};
+template <class P>
+struct LateRaw<P, true> {
+    using type = typename P::Raw;
+};
+
 // Prefetched epilogue operands of an epilogue with PREF (its Pre type).
 template <class Epi, bool = Epi::PREF>
 struct EpiPreT {
@@ -894,6 +933,8 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     constexpr int NSTG = fft_nstages(N);
     constexpr int R1 = NSTG > 0 ? fft_radix(N, false, 0) : 1;
     constexpr int RK = PAD ? R1 / 2 : R1;  // inputs per run (the rest are known zeros on the padded grid)
+    constexpr bool LATE = ProLate<Pro>::value;
+    typename LateRaw<Pro>::type late_raw[LATE ? (E / R1) * RK : 1];
     if constexpr (Pro::PREF && (E / R1) * RK <= 8) {
         // the inputs are requested before begin()'s reductions
         if (!Pro::Gate::ok(sd)) return;
@@ -910,6 +951,10 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
             for (int r = 0; r < RK; ++r)
                 v[u * R1 + r] = Pro::template combine<L>(sd, sh, raw[u * RK + r], row,
                                                          2 * ((j + u * P) + r * (N / R1)), &acc);
+        if constexpr (LATE) {
+#pragma unroll
+            for (int i = 0; i < (E / R1) * RK; ++i) late_raw[i] = raw[i];
+        }
     } else {
         if (!Pro::begin(sd, sh, npart_rr, stride)) return;
 #pragma unroll
@@ -944,6 +989,13 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
             out = mkc(T(0.5) * (s1.x + wd.y), T(0.5) * (s1.y - wd.x));
         }
         gst(Wb + ((size_t)kt * L + rb * RPW + il) * TT + kk, out);
+    }
+    if constexpr (LATE && Pro::PREF && (E / R1) * RK <= 8) {
+#pragma unroll
+        for (int u = 0; u < E / R1; ++u)
+#pragma unroll
+            for (int r = 0; r < RK; ++r)
+                Pro::template late<L>(sd, sh, late_raw[u * RK + r], row, 2 * ((j + u * P) + r * (N / R1)));
     }
     if constexpr (Pro::NACC > 0) {
         const double s = block_sum<NT>(acc, fred);
