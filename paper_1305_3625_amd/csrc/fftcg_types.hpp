@@ -13,7 +13,9 @@ namespace fftcg {
 // CG state of one solve, in device memory.  Each field has exactly one
 // writer per kernel launch (block 0 of the named kernel, or the single-block
 // check finaliser), and no other block of that launch reads it, so no
-// intra-launch synchronisation is needed.
+// intra-launch synchronisation is needed.  One exception: when the folded
+// update's grid-wide barrier gives up, every block that gave up stores the
+// same status and done values (atomically) and the solve is abandoned.
 struct SolveState {
     double rho_cur;      // r_k . r_k (r_k . z_k preconditioned)  (row-forward kernel, block 0)
     double rho_prev;     // the same for k - 1                    (update kernel, block 0)
