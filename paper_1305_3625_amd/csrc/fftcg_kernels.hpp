@@ -733,11 +733,11 @@ struct EpiCG {
 
 // The CG epilogue with the residual update folded in (FP32 only): q = A p
 // never leaves registers.  After every workgroup has published its p.q
-// partial (a grid-wide barrier; the launch is cooperative, so the whole grid
-// is resident), each workgroup forms alpha = rho / (p.q) from all partials
-// in the same order and updates r <- r - alpha q on its own rows, with the
-// r.r partials of the next iteration.  It replaces the separate update
-// kernel: one pass over q fewer, and one kernel boundary fewer.
+// partial (a grid-wide barrier; the host launches this only where the whole
+// grid fits the device at once), each workgroup forms alpha = rho / (p.q)
+// from all partials in the same order and updates r <- r - alpha q on its
+// own rows, with the r.r partials of the next iteration.  It replaces the
+// separate update kernel: one pass over q fewer, and one kernel fewer.
 template <typename W>
 struct EpiCGU : EpiCG<W> {
     static_assert(sizeof(W) == 4, "the grid-synchronised update keeps FP32 q in registers");
@@ -1274,7 +1274,8 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
             }
             return;
         }
-        // every partial, in the order of the update kernel's reduction
+        // every partial: strided per thread, then the block sum (the update
+        // kernel's order when both reduce with the same thread count)
         double spq = 0.0;
         for (int i = tid; i < (int)gridDim.x; i += NT)
             spq += __builtin_bit_cast(double, __hip_atomic_load(pq_bits + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
