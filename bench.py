@@ -22,6 +22,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -41,8 +42,10 @@ def kernel_hash():
     from paper_1305_3625_amd import build
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        # the code only: comments and blank space do not change the kernels
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            code = re.sub(r"//[^\n]*", "", f.read())
+        h.update(" ".join(code.split()).encode())
     # include directories name this checkout's path, which differs between
     # machines: only the code-generation flags count
     flags = [f for f in build.CXXFLAGS if not f.startswith("-I")]
