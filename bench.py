@@ -10,9 +10,10 @@ a grid-wide barrier, where the device allows it) and every FP64 check, until
 the certified stop rule holds.  Inputs are resident in HBM before timing.
 
 Printed as one JSON line: solves/s, matvecs/s, FFT GFLOP/s, effective HBM
-GB/s, the roofline of the dominant kernel (the column pass, timed live with
-HIP events on the stream it runs on), and the CPU oracle timed on a bounded
-sample on this host.
+GB/s, the roofline of the dominant kernel (the CG iteration's longest pass,
+timed live with start and end events recorded by each launch on the stream
+it runs on, every pass listed), and the CPU oracle timed on a bounded sample
+on this host.
 """
 
 from __future__ import annotations
@@ -31,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FFT-CG solves/s + HBM GB/s at L=2048; served p50/p99 latency vs plain FP64"
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_col_M4096_fp32_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_iteration_L2048_fp32_traffic.json")
 KERNEL_SOURCES = ["paper_1305_3625_amd/csrc/fftcg_kernels.hpp", "paper_1305_3625_amd/csrc/fftcg_dev.hpp",
                   "paper_1305_3625_amd/csrc/engine_inst.hip"]
 
@@ -66,8 +67,19 @@ def bytes_model(L, M):
     it_folded = (20 * n + W) + col + (W + 16 * n)
     chk = (28 * n + 2 * W) + (4 * W + 2 * spec) + (2 * W + 32 * n)  # FP64 check passes
     apply = (8 * n + W) + col + (W + 24 * n)          # fftcg_apply, FP32 operator
+    passes = dict(row_fwd=20 * n + W, col=col, row_inv=W + 12 * n, row_inv_upd=W + 16 * n, update=12 * n)
     return dict(col=col, iteration=it, iteration_folded=it_folded, check=chk, apply=apply,
-                per_column=16 * L + 4 * (M // 2 + 1))
+                per_column=16 * L + 4 * (M // 2 + 1), passes=passes)
+
+
+def pass_kernels(M):
+    """Kernel names (as the rocprofv3 summary lists them) of the FP32 CG
+    iteration's passes on an M-grid with zero padding."""
+    return dict(row_fwd=f"k_row_fwd<float, {M}, 1, ProCG<float, float, 256>, ByPtr, 256>",
+                col=f"k_col<float, {M}, 1, GateIter, ByPtr, 512, false>",
+                row_inv=f"k_row_inv<float, {M}, 1, EpiCG<float>, ByPtr, 256>",
+                row_inv_upd=f"k_row_inv_upd<float, {M}, 1, ByPtr, 256>",
+                update="k_update<float, 256>")
 
 
 def fft_flops_nominal(M):
@@ -694,14 +706,29 @@ def main(argv=None):
     y = torch.empty((L, L), dtype=torch.float64, device="cuda")
     passes32 = plan.profile_apply(D[0], B[0], y, reps=30, precision=binding.MIXED)
     passes64 = plan.profile_apply(D[0], B[0], y, reps=10, precision=binding.FP64)
-    t_col = passes32[1] * 1e-3
-    achieved = bm["col"] / t_col / 1e9
-    traffic = None
+    # live timing of the CG iteration's own kernels, each launch's start and
+    # end recorded by the launch on its stream; the roofline is the pass that
+    # takes longest (the dominant kernel)
+    it_ms, it_folded = plan.profile_iteration(D[0], B[0], y, reps=40, precision=binding.MIXED)
+    names = ["row_fwd", "col", "row_inv_upd" if it_folded else "row_inv", "update"]
+    kern = pass_kernels(M)
+    counted = {}
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_hash") == kernel_hash() and tr.get("L") == L:
-            traffic = tr.get("bytes_per_launch")
+            counted = tr.get("bytes_per_launch", {})
+    passes = {}
+    for nm, ms in zip(names, it_ms):
+        if ms <= 0:
+            continue
+        gbps = bm["passes"][nm] / (ms * 1e-3) / 1e9
+        passes[nm] = dict(kernel=kern[nm], ms_per_launch=round(ms, 5), bytes_per_launch=bm["passes"][nm],
+                          GBps=round(gbps, 1), frac=round(gbps / HBM_PEAK_GBPS, 4),
+                          traffic=counted.get(kern[nm]))
+    dom = max(passes, key=lambda k: passes[k]["ms_per_launch"])
+    achieved = passes[dom]["GBps"]
+    traffic = passes[dom]["traffic"]
 
     # practical HBM ceiling: the library's streaming kernels over 1 GiB, and
     # (for reference, and as the counter calibration under rocprofv3) torch's
@@ -722,9 +749,9 @@ def main(argv=None):
     copy_gbps = max(ceiling["copy"]["GBps"], torch_copy_gbps)
     progress(f"HBM probes: {ceiling}")
     by_size = stream_by_size()
-    # the column pass's working set (W both ways and the quarter spectrum,
-    # about 50 MB here) stays in the last-level cache between launches:
-    # its practical ceiling is the copy rate at that size
+    # a pass's working set (50 to 120 MB here) stays in the last-level
+    # cache between launches: its practical ceiling is the copy rate at
+    # buffers of 64 MiB or less
     resident_copy = max(v["copy"] for k, v in by_size.items() if int(k[:-3]) <= 64)
     progress(f"streaming by size: {by_size}")
 
@@ -811,15 +838,17 @@ def main(argv=None):
             "L": L, "M": M, "padded": 1, "eps": 1e-4, "tol": 1e-8, "seeds": [[3, s] for s in range(3)],
         },
         "roofline": {
-            "kernel": "k_col (column pass: forward FFT, *ghat/M^2, inverse FFT, FP32)",
+            "kernel": passes[dom]["kernel"],
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "bytes_per_launch": bm["col"],
-            "ms_per_launch": round(passes32[1], 5),
+            "bytes_per_launch": passes[dom]["bytes_per_launch"],
+            "ms_per_launch": passes[dom]["ms_per_launch"],
+            "timing": "fftcg_profile_iteration: 40 iterations, start/end events recorded by each launch",
+            "iteration_passes": passes,
             "copy_GBps": round(copy_gbps, 1),
             "frac_of_copy": round(achieved / copy_gbps, 4),
             "stream_probes": ceiling,

@@ -213,6 +213,26 @@ int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d,
                         const double* x, double* y, int reps,
                         double* ms_per_pass, void* stream);
 
+/* fftcg_profile_iteration -- measurement aid: runs `reps` (1..100)
+ * iterations of the CG iteration that fftcg_solve runs on this plan (plain
+ * CG, Sec. 3 Listing 2) on (d, b) from x = 0, without FP64 checks, and times
+ * every kernel with a start and an end event recorded by its own launch
+ * (hipExtLaunchKernel: the kernel's execution, as a kernel trace reports
+ * it).  ms_per_pass (HOST array of 4) receives the mean device milliseconds
+ * per iteration of [0] the forward row pass (with the CG prologue), [1] the
+ * column pass, [2] the row-inverse pass (with the folded update when it
+ * applies, fftcg_plan_set_grid_sync), [3] the separate update kernel (0 when
+ * folded).  *folded (HOST, may be NULL) = 1 when the update was folded.
+ * d, b: DEVICE, L*L doubles; x: DEVICE scratch of L*L doubles (the iterate,
+ * overwritten), not overlapping d or b.  Blocks until done.  FFTCG_EINVAL
+ * for the fused engine or bad arguments, and when the iterations stopped
+ * early (b = 0); FFTCG_EBREAKDOWN if they broke down; FFTCG_EDEVICE if the
+ * folded update's barrier gave up (the plan then keeps the separate
+ * kernel).                                                                 */
+int fftcg_profile_iteration(fftcg_plan_t plan, int precision, const double* d,
+                            const double* b, double* x, int reps,
+                            double* ms_per_pass, int* folded, void* stream);
+
 /* fftcg_stream_probe -- measurement aid: the HBM rate of plain streaming
  * kernels, the practical ceiling of the memory-bound passes.  kind 0 reads
  * `bytes` from src (16-byte loads, summed; dst is a sink that receives 4

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD"
 EXPORTS = [
     "fftcg_plan", "fftcg_plan_destroy", "fftcg_plan_set_engine", "fftcg_plan_set_precond",
     "fftcg_plan_set_error_target", "fftcg_plan_set_grid_sync", "fftcg_plan_get_grid_sync", "fftcg_plan_info",
-    "fftcg_apply", "fftcg_profile_apply", "fftcg_stream_probe", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
+    "fftcg_apply", "fftcg_profile_apply", "fftcg_profile_iteration", "fftcg_stream_probe", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
     "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_shutdown",
     "fftcg_server_destroy",
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
                                 ctypes.POINTER(S)]),
         "fftcg_apply": (I, [P, I, P, P, P, P]),
         "fftcg_profile_apply": (I, [P, I, P, P, P, I, ctypes.POINTER(D), P]),
+        "fftcg_profile_iteration": (I, [P, I, P, P, P, I, ctypes.POINTER(D), ctypes.POINTER(I), P]),
         "fftcg_solve": (I, [P, I, P, P, P, D, I, P, ctypes.POINTER(Info), P]),
         "fftcg_loadstep": (I, [P, P, P, P, ctypes.POINTER(I), P]),
         "fftcg_loadstep_noalloc": (I, [P, P, P, P, ctypes.POINTER(I), P]),
@@ -281,6 +282,18 @@ class Plan:
         if st != OK:
             raise FftcgError(st, "fftcg_profile_apply")
         return [ms[0], ms[1], ms[2]]
+
+    def profile_iteration(self, d, b, x, reps=20, precision=MIXED, stream=None):
+        """Mean device ms of the CG iteration's passes (row_fwd, col,
+        row_inv, separate update) over `reps` iterations from x = 0, and
+        whether the update was folded; x is scratch."""
+        ms = (ctypes.c_double * 4)()
+        folded = ctypes.c_int()
+        st = load().fftcg_profile_iteration(self.h, precision, _ptr(d), _ptr(b), _ptr(x), int(reps), ms,
+                                            ctypes.byref(folded), _stream(stream))
+        if st != OK:
+            raise FftcgError(st, "fftcg_profile_iteration")
+        return [ms[0], ms[1], ms[2], ms[3]], bool(folded.value)
 
     def solve(self, d, b, x, x0=None, tol=1e-10, maxit=10000, precision=FP64, stream=None,
               raise_on_error=True):

@@ -48,6 +48,12 @@ struct EngineOps {
     // false (and runs the separate kernels) where grid_capable is false.
     bool (*iter_grid)(int prec, const PlanTabs& t, const SlotDesc* slot, int stride, unsigned long long token,
                       hipStream_t s);
+    // one pass of a plain-CG iteration of one slot (measurement aid): 0 the
+    // forward row pass, 1 the column pass, 2 the row-inverse pass (with the
+    // folded update when grid), 3 the separate update (nothing when grid);
+    // the launch records ev0 as the kernel starts and ev1 as it ends
+    void (*iter_pass)(int prec, int pass, bool grid, const PlanTabs& t, const SlotDesc* slot, int stride,
+                      unsigned long long token, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
     // whether iter_grid applies on the current device: FP32 working
     // precision, the whole row-inverse grid resident at once, and no more
     // r.r partials per pass than the update kernel writes

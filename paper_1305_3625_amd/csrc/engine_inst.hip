@@ -2,6 +2,8 @@
 // (FFTCG_M, FFTCG_PAD) by the build script.
 #include <string.h>
 
+#include <hip/hip_ext.h>
+
 #include "engine.hpp"
 #include "fftcg_kernels.hpp"
 
@@ -120,6 +122,42 @@ bool iter_grid_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride
     hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
     hipLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, token);
     return true;
+}
+
+template <typename W>
+void iter_pass_t(int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long token,
+                 hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+    constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS, RB = G<W>::ROW_BLOCKS;
+    const ByPtr sp{slot};
+    const Tab<W> tab = tab_of<W>(pt);
+    if (pass == 0) {
+        hipExtLaunchKernelGGL((k_row_fwd<W, M, PAD, ProCG<W, W, RT>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0,
+                              tab, sp, grid ? RB : g4_blocks(), stride);
+    } else if (pass == 1) {
+        hipExtLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, e0, e1, 0,
+                              tab, sp);
+    } else if (pass == 2) {
+        if constexpr (sizeof(W) == 4) {
+            if (grid) {
+                hipExtLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab,
+                                      sp, stride, token);
+                return;
+            }
+        }
+        hipExtLaunchKernelGGL((k_row_inv<W, M, PAD, EpiCG<W>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab,
+                              sp, stride);
+    } else if (!grid) {
+        hipExtLaunchKernelGGL((k_update<W, UPD_NT>), dim3(g4_blocks()), dim3(UPD_NT), 0, s, e0, e1, 0, sp, LL * LL,
+                              RB, stride);
+    }
+}
+
+void iter_pass_fn(int prec, int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, int stride,
+                  unsigned long long token, hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+    if (prec == 0)
+        iter_pass_t<double>(pass, false, pt, slot, stride, token, e0, e1, s);
+    else
+        iter_pass_t<float>(pass, grid && G<float>::ROW_BLOCKS <= g4_blocks(), pt, slot, stride, token, e0, e1, s);
 }
 
 bool grid_capable_fn(int prec) {
@@ -284,6 +322,7 @@ const EngineOps kOps = {M,
                         &check0_fn,
                         &check0_pcg_fn,
                         &iter_grid_fn,
+                        &iter_pass_fn,
                         &grid_capable_fn};
 
 }  // namespace

@@ -404,6 +404,11 @@ extern "C" int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, s
 } FFTCG_ABI_CATCH
 
 // ---- apply -------------------------------------------------------------------
+// Wait limit of the grid-wide barrier (ticks of the 100 MHz constant clock):
+// 100 ms, far beyond the few microseconds between the first and the last
+// workgroup of a resident grid.
+constexpr long long kGridWaitTicks = 10000000;
+
 static bool overlap(const void* a, const void* b, size_t n) {
     const char* x = (const char*)a;
     const char* y = (const char*)b;
@@ -467,6 +472,90 @@ extern "C" int fftcg_profile_apply(fftcg_plan_t plan, int precision, const doubl
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
     if (rc == FFTCG_OK)
         for (int pass = 0; pass < 3; ++pass) ms_per_pass[pass] = acc[pass] / (blocks * RUN);
+    return rc;
+} FFTCG_ABI_CATCH
+
+extern "C" int fftcg_profile_iteration(fftcg_plan_t plan, int precision, const double* d, const double* b,
+                                       double* x, int reps, double* ms_per_pass, int* folded, void* stream) try {
+    if (!plan || !d || !b || !x || !ms_per_pass || reps < 1 || reps > 100) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    if (!plan->ops || plan_engine(plan) == FFTCG_ENGINE_FUSED) return FFTCG_EINVAL;
+    const size_t n = (size_t)plan->L * plan->L;
+    if (overlap(x, d, n * 8) || overlap(x, b, n * 8)) return FFTCG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const EngineOps* ops = plan->ops;
+    const bool grid = plan->grid_mode != 0 && !plan->grid_broken.load() && plan->grid_cap[precision == FFTCG_MIXED];
+    Workspace* w = plan_acquire(plan);
+    if (!w) return FFTCG_ENOMEM;
+    int rc = FFTCG_OK;
+    // a start and an end event per launch, recorded by the launch itself
+    // (the kernel's own execution, as a kernel trace reports it)
+    const int npass = grid ? 3 : 4;
+    std::vector<hipEvent_t> ev((size_t)2 * npass * reps, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            rc = FFTCG_EDEVICE;
+        }
+    do {
+        if (rc != FFTCG_OK) break;
+        // plain CG from x = 0 with nothing that would pause the iterations:
+        // no periodic check, no reliable update, an unreachable tolerance
+        fill_slot(w->h_slot, w, x, b, d);
+        w->h_slot->mask = nullptr;
+        init_state(w->h_state, plan, precision, 1e-30, 1 << 30, 0);
+        w->h_state->pcg = 0;
+        w->h_state->delta2 = 0.0;
+        w->h_state->bar_limit = kGridWaitTicks;
+        for (int i = 0; i < 4; ++i) w->h_status[i] = 0;
+        hipError_t he = hipMemcpyAsync(w->slot, w->h_slot, sizeof(SlotDesc), hipMemcpyHostToDevice, s);
+        if (he == hipSuccess) he = hipMemcpyAsync(w->st, w->h_state, sizeof(SolveState), hipMemcpyHostToDevice, s);
+        if (he == hipSuccess) he = hipMemsetAsync(x, 0, n * 8, s);
+        if (he == hipSuccess && precision == FFTCG_MIXED) {
+            he = hipMemsetAsync(w->e, 0, n * 4, s);
+            if (he == hipSuccess) launch_to_f32(d, w->d32, (int)n, s);
+        }
+        if (he != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        ops->check0(precision, plan->tabs, w->slot, 1, plan->stride, s);
+        for (int k = 0; k < reps; ++k)
+            for (int pass = 0; pass < npass; ++pass) {
+                const unsigned long long token = (grid && pass == 2) ? ++w->grid_token : 0;
+                const size_t e = 2 * ((size_t)k * npass + pass);
+                ops->iter_pass(precision, pass, grid, plan->tabs, w->slot, plan->stride, token, ev[e], ev[e + 1], s);
+            }
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(w->h_state, w->st, sizeof(SolveState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        const SolveState st = *w->h_state;
+        if (st.status == ST_EGRID) {
+            plan->grid_broken.store(1);
+            rc = FFTCG_EDEVICE;
+            break;
+        }
+        if (st.done || st.pause || st.iters != reps) {
+            rc = (st.done && st.status < 0) ? st.status : FFTCG_EINVAL;
+            break;
+        }
+        double acc[4] = {0, 0, 0, 0};
+        for (int k = 0; k < reps; ++k)
+            for (int pass = 0; pass < npass; ++pass) {
+                const size_t e = 2 * ((size_t)k * npass + pass);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, ev[e], ev[e + 1]);
+                acc[pass] += ms;
+            }
+        for (int pass = 0; pass < 4; ++pass) ms_per_pass[pass] = acc[pass] / reps;
+        if (folded) *folded = grid ? 1 : 0;
+    } while (0);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    plan_release(plan, w);
     return rc;
 } FFTCG_ABI_CATCH
 
@@ -627,11 +716,6 @@ struct ChunkPlanner {
         }
     }
 };
-
-// Wait limit of the grid-wide barrier (ticks of the 100 MHz constant clock):
-// 100 ms, far beyond the few microseconds between the first and the last
-// workgroup of a resident grid.
-constexpr long long kGridWaitTicks = 10000000;
 
 static int solve_multipass_once(fftcg_plan_t plan, Workspace* w, int precision, const double* d, const double* b,
                                 const double* x0, double tol, int maxit, double* x, fftcg_info* info,

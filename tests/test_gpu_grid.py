@@ -16,7 +16,8 @@ differently, so solutions agree to within the solves' tolerance, not bitwise.
   separate kernel; the result is bitwise the separate kernel's, also for a
   warm start given in place (x0 == x);
 * the masked operator of the fracture driver (Sec. 2) through the folded
-  path at L = 512, breaks replayed by the oracle.
+  path at L = 512, breaks replayed by the oracle;
+* repeatability, a busy device, and the iteration timing aid.
 """
 
 import json
@@ -216,4 +217,31 @@ def test_grid_with_other_stream_busy():
     assert info["status"] == binding.OK and info["error_bound"] <= 1e-8
     assert state in (binding.GRID_ON, binding.GRID_FELL_BACK)
     assert relerr(host(x), x0) <= 2e-8
+    plan.close()
+
+
+@pytest.mark.parametrize("L", [256, 2048])
+def test_profile_iteration(L):
+    """The iteration timing aid: positive pass times, the folded update
+    reported as such (no separate update pass), the separate kernel timed
+    when the plan uses it; b = 0 stops at once and is refused."""
+    import torch
+    inst = padded_instance(L, [3, 11], eps=1e-4, normal_b=True)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("profile-iteration", L)
+    d, b = dev(inst["d"]), dev(inst["b"])
+    x = torch.empty((L, L), dtype=torch.float64, device="cuda")
+    ms, folded = plan.profile_iteration(d, b, x, reps=40)
+    print(f"folded: {folded}, ms {[round(v, 4) for v in ms]}")
+    assert folded and all(v > 0 for v in ms[:3]) and ms[3] == 0.0
+    plan.set_grid_sync(0)
+    ms0, folded0 = plan.profile_iteration(d, b, x, reps=40)
+    print(f"separate: ms {[round(v, 4) for v in ms0]}")
+    assert not folded0 and all(v > 0 for v in ms0)
+    ms64, _ = plan.profile_iteration(d, b, x, reps=4, precision=binding.FP64)
+    assert all(v > 0 for v in ms64)
+    with pytest.raises(binding.FftcgError):
+        plan.profile_iteration(d, torch.zeros_like(b), x, reps=4)
+    with pytest.raises(binding.FftcgError):
+        plan.profile_iteration(d, b, x, reps=0)
     plan.close()
