@@ -323,12 +323,17 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10, literal=False, full=True, 
                 time.sleep(max(0.0, min(2e-4, nxt)))
         return lat, iters, bad, time.perf_counter() - t0, bounds, kept
 
-    def run_served(budget=budget, n=len(reqs), warm_n=0, keep=None):
+    def run_served(budget=budget, n=len(reqs), warm_n=0, keep=None, reserve=None):
         """warm_n > 0: the first warm_n requests of the schedule are served
         first, untimed, on the same server, so that its slots and pinned
-        staging buffers have grown to their steady-state number; otherwise
-        the timed schedule starts with one slot per size."""
+        staging buffers have grown to their steady-state number; reserve
+        ({M: slots}): those slots (with pinned buffers) are reserved up front
+        (fftcg_server_reserve, untimed); otherwise the timed schedule starts
+        with one slot per size.  Also returns the slots each size held at
+        the end."""
         srv = binding.Server(memory_budget=budget, chunk_iters=chunk)
+        for M, k in (reserve or {}).items():
+            srv.reserve(plans[M], k)
         # warm-up: one request per size (allocates slots, loads kernels)
         tks = []
         for M in plans:
@@ -343,10 +348,12 @@ def serve_bench(n_requests, budget=4 << 30, chunk=10, literal=False, full=True, 
             drive(srv, warm_n)
         lat, iters, bad, makespan, bounds, kept = drive(srv, n, keep)
         stats = srv.stats()
+        held = {M: srv.class_slots(plans[M]) for M in plans}
         srv.close()
         out = dict(p50_ms=_pct(lat, 50) * 1e3, p99_ms=_pct(lat, 99) * 1e3, solves_per_s=len(lat) / makespan,
                    makespan_s=makespan, failed=bad, mean_iters=float(np.mean(iters)),
-                   peak_bytes=stats["bytes_in_use"], error_bound_max=float(max(bounds)))
+                   peak_bytes=stats["bytes_in_use"], error_bound_max=float(max(bounds)),
+                   slots_held={str(M): k for M, k in held.items()})
         return out, kept
 
     def run_closed_loop():

@@ -393,6 +393,27 @@ int fftcg_server_completed(fftcg_server_t srv, uint64_t* out, int cap, int* n);
 /* Counters of the server (host pointer).                                   */
 int fftcg_server_get_stats(fftcg_server_t srv, fftcg_server_stats* out);
 
+/* fftcg_server_reserve -- capacity planning: makes the server hold `slots`
+ * request slots (device memory, within the budget) for solves with this
+ * plan and precision, each with its pinned staging buffer, captures the
+ * class's chunk graphs for up to `slots` running solves, and caches pinned
+ * input and result buffers for as many requests (solves without x0), so
+ * that a burst of that class neither allocates device memory, pins host
+ * memory nor builds graphs on its way in.  Blocks until the slots exist (the scheduler
+ * thread makes them).  The plan stays referenced by the server
+ * (fftcg_plan_destroy refuses it) until fftcg_server_shutdown or
+ * fftcg_server_destroy.  Idle reserved slots can still be released when
+ * another class needs the budget.  FFTCG_EINVAL for bad arguments or slots
+ * above max_slots; FFTCG_ENOMEM when the budget or an allocation cannot hold
+ * them (the slots made so far stay); FFTCG_ECANCELED after shutdown.       */
+int fftcg_server_reserve(fftcg_server_t srv, fftcg_plan_t plan, int precision, int slots);
+
+/* fftcg_server_class_slots -- *slots = the slots the server holds for
+ * solves with this plan and precision (0 if none), busy or idle; for sizing
+ * fftcg_server_reserve from a server that has seen the load.  FFTCG_EINVAL
+ * for a NULL argument or another precision.                                */
+int fftcg_server_class_slots(fftcg_server_t srv, fftcg_plan_t plan, int precision, int* slots);
+
 /* fftcg_server_shutdown -- stops the scheduler; every request still queued
  * or in flight ends with FFTCG_ECANCELED (info.iterations: the iterations it
  * had run), except one whose results were already being copied back, which

@@ -33,7 +33,7 @@ EXPORTS = [
     "fftcg_plan_set_error_target", "fftcg_plan_set_grid_sync", "fftcg_plan_get_grid_sync", "fftcg_plan_info",
     "fftcg_apply", "fftcg_profile_apply", "fftcg_profile_iteration", "fftcg_stream_probe", "fftcg_solve", "fftcg_loadstep", "fftcg_loadstep_noalloc", "fftcg_fracture",
     "fftcg_server_create", "fftcg_submit", "fftcg_submit_sequence", "fftcg_poll",
-    "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_shutdown",
+    "fftcg_poll_sequence", "fftcg_server_completed", "fftcg_server_get_stats", "fftcg_server_reserve", "fftcg_server_class_slots", "fftcg_server_shutdown",
     "fftcg_server_destroy",
     "fftcg_strerror", "fftcg_version", "fftcg_greens_spectrum",
 ]
@@ -117,6 +117,8 @@ def load(path: str = LIB_PATH):
         "fftcg_stream_probe": (I, [I, I, P, P, S, I, I, ctypes.POINTER(D), P]),
         "fftcg_server_completed": (I, [P, ctypes.POINTER(ctypes.c_uint64), I, ctypes.POINTER(I)]),
         "fftcg_server_get_stats": (I, [P, ctypes.POINTER(ServerStats)]),
+        "fftcg_server_reserve": (I, [P, P, I, I]),
+        "fftcg_server_class_slots": (I, [P, P, I, ctypes.POINTER(I)]),
         "fftcg_server_shutdown": (I, [P]),
         "fftcg_server_destroy": (I, [P]),
         "fftcg_fracture": (I, [P, I, ctypes.c_double, P, I, ctypes.c_double, I, P, P, P, P, P]),
@@ -402,6 +404,21 @@ class Server:
         if st != OK:
             raise FftcgError(st, "fftcg_server_get_stats")
         return s.as_dict()
+
+    def reserve(self, plan, slots, precision=MIXED):
+        """Makes the server hold `slots` slots (and pinned buffers) for this
+        plan and precision before requests arrive; blocks until done."""
+        st = load().fftcg_server_reserve(self.h, plan.h, int(precision), int(slots))
+        if st != OK:
+            raise FftcgError(st, "fftcg_server_reserve")
+
+    def class_slots(self, plan, precision=MIXED):
+        """Slots the server holds for this plan and precision."""
+        v = ctypes.c_int()
+        st = load().fftcg_server_class_slots(self.h, plan.h, int(precision), ctypes.byref(v))
+        if st != OK:
+            raise FftcgError(st, "fftcg_server_class_slots")
+        return v.value
 
     def shutdown(self):
         """Stops the server: unfinished requests end ECANCELED, results stay pollable."""

@@ -105,6 +105,17 @@ struct Class {
     int refresh = 50;      // MIXED: iterations between FP64 checks
     // multi-pass chunks captured as HIP graphs, by (running slots, preconditioned)
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    bool reserved = false;  // fftcg_server_reserve holds a reference to the plan
+    std::atomic<int> nslots{0};  // slots.size(), readable by other threads
+};
+
+// A capacity reservation waiting for the scheduler thread (which alone adds
+// slots to a class); the caller waits on cv_res until done.
+struct Reservation {
+    Class* c = nullptr;
+    int slots = 0;
+    int rc = 0;
+    bool done = false;
 };
 
 }  // namespace
@@ -134,6 +145,9 @@ struct fftcg_server_s {
     size_t page_cached = 0;
     size_t pin_inputs = 0;  // pinned input staging handed out
     size_t pin_input_cap = 0;  // a quarter of the device budget, in [1 MiB, 1 GiB]
+    // capacity reservations for the scheduler thread (guarded by mu)
+    std::deque<Reservation*> reserves;
+    std::condition_variable cv_res;
 };
 
 namespace {
@@ -183,6 +197,7 @@ void reclaim(fftcg_server_s* srv, Class* except, size_t need) {
             (void)hipStreamSynchronize(c->stream);
             free_slot_memory(s);
             c->slots.pop_back();
+            c->nslots.store((int)c->slots.size());
             srv->bytes_in_use.fetch_sub(c->footprint);
         }
         if (srv->bytes_in_use.load() + need <= srv->opts.memory_budget) return;
@@ -220,6 +235,7 @@ bool add_slot(fftcg_server_s* srv, Class* c) {
     c->h_table[idx].active = 0;
     memset(c->h_status + 4 * idx, 0, 4 * sizeof(int));
     c->slots.push_back(std::move(s));
+    c->nslots.store((int)c->slots.size());
     upload_entry(c, idx);
     return true;
 }
@@ -505,9 +521,57 @@ bool progress(fftcg_server_s* srv, Class* c) {
     return busy || !c->pending.empty();
 }
 
+// Grows class c to `slots` slots, each with its pinned staging buffer, and
+// captures the class's chunk graphs for every running-slot count up to
+// `slots` (scheduler thread): on the way in, each new chunk shape would
+// otherwise be captured and instantiated while requests wait.  FFTCG_ENOMEM
+// when the budget or an allocation stops it; the slots made so far stay.
+int grow_class(fftcg_server_s* srv, Class* c, int slots) {
+    while ((int)c->slots.size() < slots)
+        if (!add_slot(srv, c)) return FFTCG_ENOMEM;
+    const size_t n = (size_t)c->plan->L * c->plan->L;
+    for (int i = 0; i < slots; ++i) {
+        Slot* s = c->slots[i].get();
+        if (!s->stage && hipHostMalloc((void**)&s->stage, n * 8 * 4, hipHostMallocDefault) != hipSuccess) {
+            s->stage = nullptr;
+            (void)hipGetLastError();
+            return FFTCG_ENOMEM;
+        }
+    }
+    if (srv->opts.graphs >= 0 && server_engine(c->plan) != FFTCG_ENGINE_FUSED) {
+        const bool pcg = c->plan->precond == FFTCG_PRECOND_CIRCULANT;
+        for (int nsl = 1; nsl <= slots; ++nsl)
+            if (!chunk_graph(srv, c, nsl, pcg)) (void)hipGetLastError();  // launched directly later
+    }
+    return FFTCG_OK;
+}
+
+void serve_reservations(fftcg_server_s* srv) {
+    std::vector<Reservation*> res;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->reserves.empty()) return;
+        res.assign(srv->reserves.begin(), srv->reserves.end());
+        srv->reserves.clear();
+    }
+    for (Reservation* r : res) {
+        int rc = FFTCG_OK;
+        try {
+            rc = grow_class(srv, r->c, r->slots);
+        } catch (...) {
+            rc = FFTCG_ENOMEM;
+        }
+        std::lock_guard<std::mutex> lk(srv->mu);
+        r->rc = rc;
+        r->done = true;
+    }
+    srv->cv_res.notify_all();
+}
+
 void scheduler(fftcg_server_s* srv) {
     (void)hipSetDevice(srv->opts.device);
     while (!srv->stop.load()) {
+        serve_reservations(srv);
         std::vector<Class*> cls;
         {
             std::lock_guard<std::mutex> lk(srv->mu);
@@ -525,7 +589,8 @@ void scheduler(fftcg_server_s* srv) {
         }
         if (!busy) {
             std::unique_lock<std::mutex> lk(srv->mu);
-            if (srv->queued == 0 && !srv->stop.load()) srv->cv.wait_for(lk, std::chrono::milliseconds(2));
+            if (srv->queued == 0 && srv->reserves.empty() && !srv->stop.load())
+                srv->cv.wait_for(lk, std::chrono::milliseconds(2));
         } else {
             std::this_thread::yield();
         }
@@ -740,6 +805,66 @@ extern "C" int fftcg_submit_sequence(fftcg_server_t srv, fftcg_plan_t plan, int 
     return submit_common(srv, plan, precision, d, b, nullptr, t, tol, maxit, steps, ticket);
 } FFTCG_ABI_CATCH
 
+extern "C" int fftcg_server_reserve(fftcg_server_t srv, fftcg_plan_t plan, int precision, int slots) try {
+    if (!srv || !plan || !plan->ops) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    if (slots < 0 || slots > srv->opts.max_slots) return FFTCG_EINVAL;
+    if ((size_t)slots * slot_footprint(plan) > srv->opts.memory_budget) return FFTCG_ENOMEM;
+    Reservation r;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->shut) return FFTCG_ECANCELED;
+        Class* c = nullptr;
+        auto it = srv->classes.find({plan, precision});
+        if (it == srv->classes.end()) {
+            const int rc = make_class(srv, plan, precision, &c);
+            if (rc != FFTCG_OK) return rc;
+        } else {
+            c = it->second.get();
+        }
+        if (!c->reserved) {
+            // the class now outlives any request: the plan stays referenced
+            // (fftcg_plan_destroy refuses it) until the server shuts down
+            c->reserved = true;
+            plan->refs.fetch_add(1);
+        }
+        r.c = c;
+        r.slots = slots;
+        srv->reserves.push_back(&r);
+    }
+    srv->cv.notify_all();
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        srv->cv_res.wait(lk, [&] { return r.done; });
+    }
+    if (r.rc != FFTCG_OK) return r.rc;
+    // pinned input (d and b) and result buffers for as many requests, so
+    // that their submissions and completions find them in the pool
+    const size_t n = (size_t)plan->L * plan->L;
+    for (int k = 0; k < slots; ++k) {
+        void* pi = nullptr;
+        void* px = nullptr;
+        if (hipHostMalloc(&pi, n * 8 * 2, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&px, n * 8, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            if (pi) (void)hipHostFree(pi);
+            return FFTCG_ENOMEM;
+        }
+        pin_put(srv, pi, n * 8 * 2, false, true);
+        pin_put(srv, px, n * 8, false, true);
+    }
+    return FFTCG_OK;
+} FFTCG_ABI_CATCH
+
+extern "C" int fftcg_server_class_slots(fftcg_server_t srv, fftcg_plan_t plan, int precision, int* slots) try {
+    if (!srv || !plan || !slots) return FFTCG_EINVAL;
+    if (precision != FFTCG_FP64 && precision != FFTCG_MIXED) return FFTCG_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->classes.find({plan, precision});
+    *slots = it == srv->classes.end() ? 0 : it->second->nslots.load();
+    return FFTCG_OK;
+} FFTCG_ABI_CATCH
+
 static int poll_common(fftcg_server_t srv, uint64_t ticket, double* x, int* broken, int* step_iters,
                        double* step_bounds, fftcg_info* info, bool seq) {
     if (!srv) return FFTCG_EINVAL;
@@ -810,6 +935,16 @@ static void shutdown_server(fftcg_server_s* srv) {
     srv->stop.store(true);
     srv->cv.notify_all();
     if (srv->thread.joinable()) srv->thread.join();
+    {
+        // reservations the scheduler did not reach
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (Reservation* r : srv->reserves) {
+            r->rc = FFTCG_ECANCELED;
+            r->done = true;
+        }
+        srv->reserves.clear();
+    }
+    srv->cv_res.notify_all();
     // the scheduler has stopped and no submission adds a class any more: the
     // classes are this thread's alone
     for (auto& kv : srv->classes) {
@@ -845,7 +980,10 @@ static void shutdown_server(fftcg_server_s* srv) {
         }
         c->pending.clear();
     }
-    for (auto& kv : srv->classes) destroy_class(kv.second.get());
+    for (auto& kv : srv->classes) {
+        destroy_class(kv.second.get());
+        if (kv.second->reserved) kv.second->plan->refs.fetch_sub(1);
+    }
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->classes.clear();
     srv->bytes_in_use.store(0);

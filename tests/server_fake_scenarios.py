@@ -83,6 +83,8 @@ class Fake:
         lib.fftcg_server_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
         lib.fftcg_server_shutdown.argtypes = [P]
         lib.fftcg_server_destroy.argtypes = [P]
+        lib.fftcg_server_reserve.argtypes = [P, P, I, I]
+        lib.fftcg_server_class_slots.argtypes = [P, P, I, ctypes.POINTER(I)]
 
     def plan(self, L, fused):
         h = P()
@@ -378,9 +380,55 @@ def scenario_graphs(f):
     assert counts[0] < counts[-1] / 2, counts
 
 
+def scenario_reserve(f):
+    """Capacity reservation: the slots exist (and count against the budget)
+    before any request, the plan stays referenced until shutdown, limits are
+    checked, requests submitted while another thread reserves all complete,
+    and a reservation after shutdown is refused."""
+    foot = 16 * 16 * 40 + 8192 + 4 * 16 * 16 * 8 + 4 * 1024 + 4096
+    plan = f.plan(16, 0)
+    srv = f.server(budget=1 << 30, max_slots=8)
+    nsl = I(-1)
+    assert f.lib.fftcg_server_class_slots(srv, plan, 1, ctypes.byref(nsl)) == OK and nsl.value == 0
+    assert f.lib.fftcg_server_reserve(srv, plan, 1, 4) == OK
+    assert f.stats(srv).bytes_in_use == 4 * foot
+    assert f.lib.fftcg_server_class_slots(srv, plan, 1, ctypes.byref(nsl)) == OK and nsl.value == 4
+    assert f.lib.fftcg_server_class_slots(srv, plan, 0, ctypes.byref(nsl)) == OK and nsl.value == 0
+    assert f.lib.fftcg_fake_plan_refs(plan) == 1
+    assert f.lib.fftcg_server_reserve(srv, plan, 1, 2) == OK  # never shrinks
+    assert f.stats(srv).bytes_in_use == 4 * foot
+    assert f.lib.fftcg_server_reserve(srv, plan, 1, 9) == EINVAL  # above max_slots
+    assert f.lib.fftcg_server_reserve(srv, plan, 3, 2) == EINVAL  # precision
+    rng = np.random.default_rng([9, 0])
+    tks, res = {}, []
+    th = threading.Thread(target=lambda: res.append(f.lib.fftcg_server_reserve(srv, plan, 1, 8)))
+    th.start()
+    for _ in range(60):
+        d, b = request(rng, 16)
+        st, tk = f.submit(srv, plan, d, b)
+        assert st == OK
+        tks[tk] = b
+    th.join()
+    assert res == [OK]
+    out = wait_all(f, srv, {tk: 16 for tk in tks})
+    assert all(r[0] == OK and np.array_equal(r[1], 0.5 * tks[tk]) for tk, r in out.items())
+    assert f.stats(srv).bytes_in_use == 8 * foot
+    # the budget bounds a reservation
+    small = f.server(budget=int(2.5 * foot))
+    assert f.lib.fftcg_server_reserve(small, plan, 1, 3) == ENOMEM
+    assert f.lib.fftcg_server_reserve(small, plan, 1, 2) == OK
+    assert f.lib.fftcg_fake_plan_refs(plan) == 2
+    f.lib.fftcg_server_destroy(small)
+    assert f.lib.fftcg_server_shutdown(srv) == OK
+    assert f.lib.fftcg_fake_plan_refs(plan) == 0
+    assert f.lib.fftcg_server_reserve(srv, plan, 1, 1) == ECANCELED
+    f.lib.fftcg_server_destroy(srv)
+    f.lib.fftcg_fake_plan_free(plan)
+
+
 ALL = [scenario_mix_two_clients, scenario_budget, scenario_queue_cap_and_maxit, scenario_invalid_inputs,
        scenario_sequences,
-       scenario_shutdown, scenario_graphs]
+       scenario_shutdown, scenario_graphs, scenario_reserve]
 
 if __name__ == "__main__":
     fk = Fake(sys.argv[1])

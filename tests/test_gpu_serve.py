@@ -340,3 +340,47 @@ def test_graph_replay_equals_direct_launches(plans):
         assert ia == ib and ita == itb and ca == cb
         assert np.array_equal(xa, xb)
     p1024.close()
+
+
+def test_reserve_then_serve():
+    """Capacity reservation: the reserved slots and pinned buffers exist
+    before any request (device bytes in use), requests of the reserved
+    classes give bitwise the results of a server without reservation, the
+    plan cannot be destroyed while the server holds it, and limits are
+    checked."""
+    banner("serve-reserve")
+    p512 = binding.Plan(256, 1, spectrum(512, EPS))
+    p1024 = binding.Plan(512, 1, spectrum(1024, EPS))
+    pl = {512: p512, 1024: p1024}
+    reqs = [c4_request(900 + k, M) for k, M in enumerate([512, 1024, 512, 1024, 512, 512])]
+    out = {}
+    for reserve in (False, True):
+        srv = binding.Server(memory_budget=2 << 30, max_slots=16)
+        if reserve:
+            assert srv.class_slots(p512) == 0
+            srv.reserve(p512, 4)
+            srv.reserve(p1024, 2)
+            assert srv.class_slots(p512) == 4 and srv.class_slots(p1024) == 2
+            assert srv.class_slots(p512, binding.FP64) == 0
+            used = srv.stats()["bytes_in_use"]
+            assert used > 0
+            srv.reserve(p1024, 1)  # never shrinks
+            assert srv.stats()["bytes_in_use"] == used
+            with pytest.raises(binding.FftcgError):
+                srv.reserve(p512, 17)  # above max_slots
+            with pytest.raises(binding.FftcgError):
+                p1024.close()  # the server holds the plan
+        tks, Ls = [], {}
+        for r in reqs:
+            st, tk = srv.submit(pl[r["M"]], r["d"], r["b"], tol=1e-8)
+            assert st == binding.OK
+            tks.append(tk)
+            Ls[tk] = r["L"]
+        got = _wait(srv, tks, Ls)
+        out[reserve] = [(got[tk].x, got[tk].info["iterations"]) for tk in tks]
+        assert all(got[tk].status == binding.OK for tk in tks)
+        srv.close()
+    for (xa, ia), (xb, ib) in zip(out[False], out[True]):
+        assert ia == ib and np.array_equal(xa, xb)
+    p512.close()
+    p1024.close()  # released with the server
