@@ -165,9 +165,9 @@ int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, double tau);
  *          registers, all workgroups meet at a grid-wide barrier (the launch
  *          is cooperative) once their p.q partials are stored, and then
  *          update their own rows.  q never reaches memory and one kernel per
- *          iteration is saved.  FP32 working precision (FFTCG_MIXED) without
- *          a preconditioner, on grids whose row-inverse pass is resident as
- *          a whole (fftcg_plan_get_grid_sync reports where).
+ *          iteration is saved.  Both precisions, without a preconditioner,
+ *          on grids whose row-inverse pass is resident as a whole
+ *          (fftcg_plan_get_grid_sync reports where).
  *   mode 0: the separate update kernel (as server classes always use).
  *   mode 2: as mode 1 with the barrier's wait limit at zero, so that
  *          workgroups give up at once; for tests of the fallback below.

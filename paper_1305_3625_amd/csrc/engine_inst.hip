@@ -107,13 +107,8 @@ void iter_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, in
 // partials.  RB <= g4_blocks() (grid_capable_fn), so after an FP64 check,
 // which writes g4_blocks() of them (|r|^2 first, zeros after), the first RB
 // still hold the whole sum.
-bool iter_grid_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long token,
-                  hipStream_t s) {
-    if (prec == 0 || G<float>::ROW_BLOCKS > g4_blocks()) {
-        iter_fn(prec, pt, slot, 1, stride, s);
-        return false;
-    }
-    using W = float;
+template <typename W>
+void iter_grid_t(const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long token, hipStream_t s) {
     constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS, RB = G<W>::ROW_BLOCKS;
     const ByPtr sp{slot};
     const Tab<W> tab = tab_of<W>(pt);
@@ -121,6 +116,19 @@ bool iter_grid_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride
                        stride);
     hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
     hipLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, token);
+}
+
+bool iter_grid_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long token,
+                  hipStream_t s) {
+    const bool fits = prec == 0 ? G<double>::ROW_BLOCKS <= g4_blocks() : G<float>::ROW_BLOCKS <= g4_blocks();
+    if (!fits) {
+        iter_fn(prec, pt, slot, 1, stride, s);
+        return false;
+    }
+    if (prec == 0)
+        iter_grid_t<double>(pt, slot, stride, token, s);
+    else
+        iter_grid_t<float>(pt, slot, stride, token, s);
     return true;
 }
 
@@ -137,12 +145,10 @@ void iter_pass_t(int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, 
         hipExtLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, e0, e1, 0,
                               tab, sp);
     } else if (pass == 2) {
-        if constexpr (sizeof(W) == 4) {
-            if (grid) {
-                hipExtLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab,
-                                      sp, stride, token);
-                return;
-            }
+        if (grid) {
+            hipExtLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab, sp,
+                                  stride, token);
+            return;
         }
         hipExtLaunchKernelGGL((k_row_inv<W, M, PAD, EpiCG<W>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab,
                               sp, stride);
@@ -155,18 +161,17 @@ void iter_pass_t(int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, 
 void iter_pass_fn(int prec, int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, int stride,
                   unsigned long long token, hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
     if (prec == 0)
-        iter_pass_t<double>(pass, false, pt, slot, stride, token, e0, e1, s);
+        iter_pass_t<double>(pass, grid && G<double>::ROW_BLOCKS <= g4_blocks(), pt, slot, stride, token, e0, e1, s);
     else
         iter_pass_t<float>(pass, grid && G<float>::ROW_BLOCKS <= g4_blocks(), pt, slot, stride, token, e0, e1, s);
 }
 
-bool grid_capable_fn(int prec) {
-    using W = float;
+template <typename W>
+bool grid_capable_t() {
     constexpr int RT = G<W>::ROW_THREADS, RB = G<W>::ROW_BLOCKS;
-    if (prec == 0 || RB > g4_blocks()) return false;
-    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (RB > g4_blocks()) return false;
+    int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return false;
     const auto kern = k_row_inv_upd<W, M, PAD, ByPtr, RT>;
@@ -174,6 +179,10 @@ bool grid_capable_fn(int prec) {
         hipSuccess)
         return false;
     return (long)per_cu * cus >= RB;
+}
+
+bool grid_capable_fn(int prec) {
+    return prec == 0 ? grid_capable_t<double>() : grid_capable_t<float>();
 }
 
 void iter_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {

@@ -731,8 +731,8 @@ struct EpiCG {
     }
 };
 
-// The CG epilogue with the residual update folded in (FP32 only): q = A p
-// never leaves registers.  After every workgroup has published its p.q
+// The CG epilogue with the residual update folded in: q = A p never leaves
+// registers.  After every workgroup has published its p.q
 // partial (a grid-wide barrier; the host launches this only where the whole
 // grid fits the device at once), each workgroup forms alpha = rho / (p.q)
 // from all partials in the same order and updates r <- r - alpha q on its
@@ -740,7 +740,6 @@ struct EpiCG {
 // separate update kernel: one pass over q fewer, and one kernel fewer.
 template <typename W>
 struct EpiCGU : EpiCG<W> {
-    static_assert(sizeof(W) == 4, "the grid-synchronised update keeps FP32 q in registers");
     static constexpr bool UPD = true;
 };
 template <class E, class = void>
@@ -1212,8 +1211,13 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
         for (int r = 0; r < RK; ++r) {
             const int n = (j + u * P) + r * (N / RL);
             if constexpr (UPD) {
-                qk[u * RK + r] = Epi::template outq<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y,
-                                                       pre[u * RK + r], acc);
+                // FP32 prefetched p and d with the spectrum; FP64 reads them here
+                typename Epi::Pre pr;
+                if constexpr (Epi::PREF)
+                    pr = pre[u * RK + r];
+                else
+                    pr = Epi::template pre<L>(sd, row, 2 * n);
+                qk[u * RK + r] = Epi::template outq<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, pr, acc);
             } else if constexpr (Epi::PREF) {
                 Epi::template out2p<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, pre[u * RK + r], acc);
             } else {

@@ -7,7 +7,8 @@ folded form computes the same alpha from the same p.q partials in the same
 order and the same r update; only the r.r partial sums are grouped
 differently, so solutions agree to within the solves' tolerance, not bitwise.
 
-* which grids and precisions take it (FP32 working precision only);
+* which grids and precisions take it;
+* FP64 solves folded and separate against the oracle;
 * full-size C3 instance, folded and separate, both against the oracle's
   stored solution samples;
 * L = 256 against the oracle's solution run to stagnation;
@@ -51,7 +52,8 @@ def test_grid_sync_states():
     plan = binding.Plan(L, 1, spectrum(2 * L, 1e-4))
     banner("grid-states", L)
     assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
-    assert plan.grid_sync(binding.FP64) == binding.GRID_UNSUPPORTED
+    # FP64 at M = 4096: 2 workgroups of the pass per CU, fewer than it has
+    assert plan.grid_sync(binding.FP64) in (binding.GRID_UNSUPPORTED, binding.GRID_ON)
     plan.set_grid_sync(0)
     assert plan.grid_sync(binding.MIXED) == binding.GRID_OFF
     plan.set_grid_sync(1)
@@ -99,6 +101,33 @@ def test_grid_L256_against_oracle():
         print(f"mode {mode}: iters {info['iterations']} error {err:.3e} (oracle bound {rinfo['bound']:.1e})")
         assert info["status"] == binding.OK
         assert err <= 1e-8 + rinfo["bound"]
+    plan.close()
+
+
+@pytest.mark.parametrize("L", [256, 512])
+def test_grid_fp64_against_oracle(L):
+    """FP64 solves (the periodic and padded FP64 workloads' precision) with
+    the folded update and with the separate kernel, against the oracle."""
+    import torch
+    inst = padded_instance(L, [3, 12, L], eps=1e-3)
+    xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 1)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("grid-fp64", L)
+    assert plan.grid_sync(binding.FP64) == binding.GRID_ON
+    for mode in (1, 0):
+        plan.set_grid_sync(mode)
+        x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+        info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, tol=1e-10, precision=binding.FP64)
+        err = relerr(host(x), xr)
+        print(f"mode {mode}: iters {info['iterations']} error {err:.3e}")
+        assert info["status"] == binding.OK and err <= 1e-10 + rinfo["bound"]
+    ms, folded = plan.profile_iteration(dev(inst["d"]), dev(inst["b"]), torch.empty_like(x), reps=8,
+                                        precision=binding.FP64)
+    assert not folded  # mode 0 was set last
+    plan.set_grid_sync(1)
+    ms, folded = plan.profile_iteration(dev(inst["d"]), dev(inst["b"]), torch.empty_like(x), reps=8,
+                                        precision=binding.FP64)
+    assert folded and ms[3] == 0.0 and all(v > 0 for v in ms[:3])
     plan.close()
 
 
