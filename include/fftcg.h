@@ -171,7 +171,7 @@ int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, double tau);
  *   mode 0: the separate update kernel (as server classes always use).
  *   mode 2: as mode 1 with the barrier's wait limit at zero, so that
  *          workgroups give up at once; for tests of the fallback below.
- * A barrier that is not met within its wait limit (100 ms; another stream's
+ * A barrier that is not met within its wait limit (20 ms; another stream's
  * work can hold part of the device) abandons the solve, which is then
  * repeated from its start with mode 0 semantics; the plan keeps the separate
  * kernel from then on, until this call sets a mode again.  The result is

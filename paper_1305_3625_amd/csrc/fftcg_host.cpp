@@ -405,9 +405,9 @@ extern "C" int fftcg_plan_info(fftcg_plan_t plan, int* L, int* M, int* padded, s
 
 // ---- apply -------------------------------------------------------------------
 // Wait limit of the grid-wide barrier (ticks of the 100 MHz constant clock):
-// 100 ms, far beyond the few microseconds between the first and the last
-// workgroup of a resident grid.
-constexpr long long kGridWaitTicks = 10000000;
+// 20 ms, a thousand times the 8-20 us between the first and the last
+// arrival in a resident grid; a solve abandoned at a barrier costs this once.
+constexpr long long kGridWaitTicks = 2000000;
 
 static bool overlap(const void* a, const void* b, size_t n) {
     const char* x = (const char*)a;

@@ -274,3 +274,43 @@ def test_profile_iteration(L):
     with pytest.raises(binding.FftcgError):
         plan.profile_iteration(d, b, x, reps=0)
     plan.close()
+
+
+def test_grid_two_solves_concurrently():
+    """Two host threads solve with one plan at once, each on its own stream
+    (two workspaces): two folded row-inverse passes may then compete for
+    the device.  Whether their barriers complete or give up (the solve then
+    repeats with the separate kernel), both results match the separate
+    kernel's to within the tolerance."""
+    import threading
+    import torch
+    L = 2048
+    insts = [c3_instance(s) for s in (0, 1)]
+    plan = binding.Plan(L, 1, insts[0]["ghat"])
+    banner("grid-two-streams", L)
+    ref = [_solve(plan, inst, 0)[0] for inst in insts]
+    plan.set_grid_sync(1)
+    D = [dev(i["d"]) for i in insts]
+    B = [dev(i["b"]) for i in insts]
+    X = [torch.zeros((L, L), dtype=torch.float64, device="cuda") for _ in insts]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    infos = [None, None]
+    torch.cuda.synchronize()
+
+    def run(k):
+        infos[k] = plan.solve(D[k], B[k], X[k], tol=1e-8, precision=binding.MIXED, stream=streams[k],
+                              raise_on_error=False)
+
+    th = [threading.Thread(target=run, args=(k,)) for k in (0, 1)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    state = plan.grid_sync(binding.MIXED)
+    print(f"state {state}, iters {[i['iterations'] for i in infos]}")
+    assert state in (binding.GRID_ON, binding.GRID_FELL_BACK)
+    for k in (0, 1):
+        assert infos[k]["status"] == binding.OK and infos[k]["error_bound"] <= 1e-8
+        assert relerr(host(X[k]), ref[k]) <= 2e-8
+    plan.close()
