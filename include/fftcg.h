@@ -162,9 +162,10 @@ int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, double tau);
  * in fftcg_solve and fftcg_fracture (Sec. 3, the r update of Listing 2).
  *   mode 1 (default): where the device allows it, the update r <- r - alpha q
  *          runs inside the row-inverse pass: each workgroup keeps its q in
- *          registers, all workgroups meet at a grid-wide barrier (the launch
- *          is cooperative) once their p.q partials are stored, and then
- *          update their own rows.  q never reaches memory and one kernel per
+ *          registers, all workgroups meet at a grid-wide barrier (the
+ *          plan checks that the pass's whole grid fits the device at once)
+ *          once their p.q partials are stored, and then update their own
+ *          rows.  q never reaches memory and one kernel per
  *          iteration is saved.  Both precisions, without a preconditioner,
  *          on grids whose row-inverse pass is resident as a whole
  *          (fftcg_plan_get_grid_sync reports where).
