@@ -6,7 +6,8 @@ Workload: mixed-precision solves on the zero-padded 2048 x 2048 grid
 error target 1e-8 (three seeded instances, cycled).  A step is one complete
 solve: initial FP64 residual, every CG iteration (row R2C, column
 FFT*ghat*IFFT, row C2R + epilogue with the residual update folded in behind
-a grid-wide barrier, where the device allows it) and every FP64 check, until
+a grid-wide barrier, where the device allows it, and within a chunk the next
+iteration's row R2C in the same pass) and every FP64 check, until
 the certified stop rule holds.  Inputs are resident in HBM before timing.
 
 Printed as one JSON line: solves/s, matvecs/s, FFT GFLOP/s, effective HBM
@@ -65,10 +66,16 @@ def bytes_model(L, M):
     # single solves with the update folded into the row-inverse pass: it
     # reads r and writes r instead of writing q, and the update pass is gone
     it_folded = (20 * n + W) + col + (W + 16 * n)
+    # the turn pass (row-inverse with the folded update, then the next
+    # iteration's forward row pass on the same rows): r and p are not read
+    # back, so per iteration col + turn moves 8 n bytes less again
+    turn = 2 * W + 28 * n
+    it_turn = col + turn
     chk = (28 * n + 2 * W) + (4 * W + 2 * spec) + (2 * W + 32 * n)  # FP64 check passes
     apply = (8 * n + W) + col + (W + 24 * n)          # fftcg_apply, FP32 operator
-    passes = dict(row_fwd=20 * n + W, col=col, row_inv=W + 12 * n, row_inv_upd=W + 16 * n, update=12 * n)
-    return dict(col=col, iteration=it, iteration_folded=it_folded, check=chk, apply=apply,
+    passes = dict(row_fwd=20 * n + W, col=col, row_inv=W + 12 * n, row_inv_upd=W + 16 * n, update=12 * n,
+                  turn=turn)
+    return dict(col=col, iteration=it, iteration_folded=it_folded, iteration_turn=it_turn, check=chk, apply=apply,
                 per_column=16 * L + 4 * (M // 2 + 1), passes=passes)
 
 
@@ -79,7 +86,8 @@ def pass_kernels(M):
                 col=f"k_col<float, {M}, 1, GateIter, ByPtr, 512, false>",
                 row_inv=f"k_row_inv<float, {M}, 1, EpiCG<float>, ByPtr, 256>",
                 row_inv_upd=f"k_row_inv_upd<float, {M}, 1, ByPtr, 256>",
-                update="k_update<float, 256>")
+                update="k_update<float, 256>",
+                turn=f"k_row_turn<float, {M}, 1, ByPtr, 256>")
 
 
 def fft_flops_nominal(M):
@@ -706,8 +714,10 @@ def main(argv=None):
     matvecs = sum(iters) + sum(checks)
     bm = bytes_model(L, M)
     grid_state = plan.grid_sync(binding.MIXED)
-    folded = grid_state == binding.GRID_ON
-    bytes_total = sum(iters) * bm["iteration_folded" if folded else "iteration"] + sum(checks) * bm["check"]
+    folded = grid_state in (binding.GRID_ON, binding.GRID_ON_TURN)
+    turn = grid_state == binding.GRID_ON_TURN
+    it_key = "iteration_turn" if turn else ("iteration_folded" if folded else "iteration")
+    bytes_total = sum(iters) * bm[it_key] + sum(checks) * bm["check"]
 
     # live per-pass timing of one product (HIP events on the launch stream)
     y = torch.empty((L, L), dtype=torch.float64, device="cuda")
@@ -717,7 +727,7 @@ def main(argv=None):
     # end recorded by the launch on its stream; the roofline is the pass that
     # takes longest (the dominant kernel)
     it_ms, it_folded = plan.profile_iteration(D[0], B[0], y, reps=40, precision=binding.MIXED)
-    names = ["row_fwd", "col", "row_inv_upd" if it_folded else "row_inv", "update"]
+    names = ["row_fwd", "col", "row_inv_upd" if it_folded else "row_inv", "update", "turn"]
     kern = pass_kernels(M)
     counted = {}
     if os.path.exists(TRAFFIC_FILE):
@@ -854,7 +864,8 @@ def main(argv=None):
             "traffic": traffic,
             "bytes_per_launch": passes[dom]["bytes_per_launch"],
             "ms_per_launch": passes[dom]["ms_per_launch"],
-            "timing": "fftcg_profile_iteration: 40 iterations, start/end events recorded by each launch",
+            "timing": "fftcg_profile_iteration: 40 iterations in a solve's launch order (with the turn pass: "
+                      "row_fwd, col, (turn, col) x 39, row_inv_upd), start/end events recorded by each launch",
             "iteration_passes": passes,
             "copy_GBps": round(copy_gbps, 1),
             "frac_of_copy": round(achieved / copy_gbps, 4),
@@ -866,6 +877,7 @@ def main(argv=None):
         },
         "cpu_baseline": cpu,
         "update_folded": folded,
+        "turn_pass": turn,
         "grid_sync_state": grid_state,
         "iterations_mean": round(float(np.mean(iters)), 2),
         "checks_mean": round(float(np.mean(checks)), 2),

@@ -169,9 +169,16 @@ int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, double tau);
  *          iteration is saved.  Both precisions, without a preconditioner,
  *          on grids whose row-inverse pass is resident as a whole
  *          (fftcg_plan_get_grid_sync reports where).
+ *          Where the device also holds the whole grid of the turn pass,
+ *          the row-inverse pass of every iteration but the last of a chunk
+ *          goes on, after a second grid-wide barrier (for r.r and beta),
+ *          into the next iteration's forward row pass on the same rows
+ *          (p <- r + beta p, the pending x update, the row transform), so
+ *          that r and p are not read back from memory.
  *   mode 0: the separate update kernel (as server classes always use).
  *   mode 2: as mode 1 with the barrier's wait limit at zero, so that
  *          workgroups give up at once; for tests of the fallback below.
+ *   mode 3: as mode 1 without the turn pass.
  * A barrier that is not met within its wait limit (20 ms; another stream's
  * work can hold part of the device) abandons the solve, which is then
  * repeated from its start with mode 0 semantics; the plan keeps the separate
@@ -185,6 +192,7 @@ int fftcg_plan_set_grid_sync(fftcg_plan_t plan, int mode);
 #define FFTCG_GRID_OFF         1 /* supported, mode 0                       */
 #define FFTCG_GRID_ON          2 /* supported and used by later solves      */
 #define FFTCG_GRID_FELL_BACK   3 /* a barrier gave up; separate kernel used */
+#define FFTCG_GRID_ON_TURN     4 /* as FFTCG_GRID_ON, with the turn pass    */
 
 /* fftcg_plan_get_grid_sync -- *state = one of FFTCG_GRID_* for solves in
  * `precision` on this plan.  FFTCG_EINVAL for a NULL argument or another
@@ -219,14 +227,19 @@ int fftcg_profile_apply(fftcg_plan_t plan, int precision, const double* d,
  * CG, Sec. 3 Listing 2) on (d, b) from x = 0, without FP64 checks, and times
  * every kernel with a start and an end event recorded by its own launch
  * (hipExtLaunchKernel: the kernel's execution, as a kernel trace reports
- * it).  ms_per_pass (HOST array of 4) receives the mean device milliseconds
- * per iteration of [0] the forward row pass (with the CG prologue), [1] the
+ * it).  ms_per_pass (HOST array of 5) receives the mean device milliseconds
+ * per launch of [0] the forward row pass (with the CG prologue), [1] the
  * column pass, [2] the row-inverse pass (with the folded update when it
  * applies, fftcg_plan_set_grid_sync), [3] the separate update kernel (0 when
- * folded).  *folded (HOST, may be NULL) = 1 when the update was folded.
+ * folded), [4] the turn pass (0 when not used).  The launches follow a
+ * solve's chunk: with the turn pass, row_fwd, col, (turn, col) x (reps - 1),
+ * row_inv (so [0] and [2] are single launches; reps >= 2), else reps times
+ * each pass.  *folded (HOST, may be NULL) = 0 separate update, 1 folded,
+ * 2 folded with the turn pass.
  * d, b: DEVICE, L*L doubles; x: DEVICE scratch of L*L doubles (the iterate,
  * overwritten), not overlapping d or b.  Blocks until done.  FFTCG_EINVAL
- * for the fused engine or bad arguments, and when the iterations stopped
+ * for the fused engine or bad arguments (reps = 1 with the turn pass), and
+ * when the iterations stopped
  * early (b = 0); FFTCG_EBREAKDOWN if they broke down; FFTCG_EDEVICE if the
  * folded update's barrier gave up (the plan then keeps the separate
  * kernel).                                                                 */

@@ -22,7 +22,7 @@ EAGAIN, EDEVICE, ENOTFOUND, ECANCELED = -6, -7, -8, -9
 FP64, MIXED = 0, 1
 ENGINE_AUTO, ENGINE_MULTIPASS, ENGINE_FUSED = 0, 1, 2
 PRECOND_NONE, PRECOND_CIRCULANT = 0, 1
-GRID_UNSUPPORTED, GRID_OFF, GRID_ON, GRID_FELL_BACK = 0, 1, 2, 3
+GRID_UNSUPPORTED, GRID_OFF, GRID_ON, GRID_FELL_BACK, GRID_ON_TURN = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "ENOCONV",
                 -5: "EBREAKDOWN", -6: "EAGAIN", -7: "EDEVICE", -8: "ENOTFOUND", -9: "ECANCELED"}
@@ -223,13 +223,14 @@ class Plan:
 
     def set_grid_sync(self, mode: int):
         """Update folded into the row-inverse pass behind a grid barrier:
-        1 on (default), 0 off, 2 on with a zero wait limit (fallback tests)."""
+        1 on (default; with the turn pass where it fits), 0 off, 2 as 1 with a
+        zero wait limit (fallback tests), 3 on without the turn pass."""
         st = load().fftcg_plan_set_grid_sync(self.h, int(mode))
         if st != OK:
             raise FftcgError(st, "fftcg_plan_set_grid_sync")
 
     def grid_sync(self, precision: int) -> int:
-        """One of GRID_UNSUPPORTED, GRID_OFF, GRID_ON, GRID_FELL_BACK."""
+        """One of GRID_UNSUPPORTED, GRID_OFF, GRID_ON, GRID_FELL_BACK, GRID_ON_TURN."""
         v = ctypes.c_int()
         st = load().fftcg_plan_get_grid_sync(self.h, int(precision), ctypes.byref(v))
         if st != OK:
@@ -286,16 +287,17 @@ class Plan:
         return [ms[0], ms[1], ms[2]]
 
     def profile_iteration(self, d, b, x, reps=20, precision=MIXED, stream=None):
-        """Mean device ms of the CG iteration's passes (row_fwd, col,
-        row_inv, separate update) over `reps` iterations from x = 0, and
-        whether the update was folded; x is scratch."""
-        ms = (ctypes.c_double * 4)()
+        """Mean device ms per launch of the CG iteration's passes (row_fwd,
+        col, row_inv, separate update, turn) over `reps` iterations from
+        x = 0, and 0 / 1 / 2: separate update / folded / folded with the turn
+        pass; x is scratch."""
+        ms = (ctypes.c_double * 5)()
         folded = ctypes.c_int()
         st = load().fftcg_profile_iteration(self.h, precision, _ptr(d), _ptr(b), _ptr(x), int(reps), ms,
                                             ctypes.byref(folded), _stream(stream))
         if st != OK:
             raise FftcgError(st, "fftcg_profile_iteration")
-        return [ms[0], ms[1], ms[2], ms[3]], bool(folded.value)
+        return [ms[0], ms[1], ms[2], ms[3], ms[4]], int(folded.value)
 
     def solve(self, d, b, x, x0=None, tol=1e-10, maxit=10000, precision=FP64, stream=None,
               raise_on_error=True):

@@ -50,14 +50,25 @@ struct EngineOps {
                       hipStream_t s);
     // one pass of a plain-CG iteration of one slot (measurement aid): 0 the
     // forward row pass, 1 the column pass, 2 the row-inverse pass (with the
-    // folded update when grid), 3 the separate update (nothing when grid);
-    // the launch records ev0 as the kernel starts and ev1 as it ends
+    // folded update when grid), 3 the separate update (nothing when grid),
+    // 4 the turn pass (grid only; tokens token and token + 1); the launch
+    // records ev0 as the kernel starts and ev1 as it ends
     void (*iter_pass)(int prec, int pass, bool grid, const PlanTabs& t, const SlotDesc* slot, int stride,
                       unsigned long long token, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
-    // whether iter_grid applies on the current device: FP32 working
-    // precision, the whole row-inverse grid resident at once, and no more
-    // r.r partials per pass than the update kernel writes
+    // whether iter_grid applies on the current device: the whole
+    // row-inverse grid resident at once, and no more r.r partials per pass
+    // than the update kernel writes
     bool (*grid_capable)(int prec);
+    // K (>= 1) such iterations of a single slot, as a chunk: with turn, the
+    // row-inverse pass of every iteration but the last goes on into the next
+    // iteration's forward row pass (k_row_turn), so the chunk launches
+    // row_fwd, col, (turn, col) x (K - 1), row_inv; without it, K times
+    // iter_grid.  *token is advanced past every token the launches use.
+    void (*iter_grid_chunk)(int prec, const PlanTabs& t, const SlotDesc* slot, int stride,
+                            unsigned long long* token, int K, bool turn, hipStream_t s);
+    // whether the turn pass is resident as a whole as well (implies
+    // grid_capable)
+    bool (*turn_capable)(int prec);
 };
 
 const EngineOps* find_engine(int M, int pad);

@@ -152,9 +152,13 @@ void iter_pass_t(int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, 
         }
         hipExtLaunchKernelGGL((k_row_inv<W, M, PAD, EpiCG<W>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab,
                               sp, stride);
-    } else if (!grid) {
-        hipExtLaunchKernelGGL((k_update<W, UPD_NT>), dim3(g4_blocks()), dim3(UPD_NT), 0, s, e0, e1, 0, sp, LL * LL,
-                              RB, stride);
+    } else if (pass == 3) {
+        if (!grid)
+            hipExtLaunchKernelGGL((k_update<W, UPD_NT>), dim3(g4_blocks()), dim3(UPD_NT), 0, s, e0, e1, 0, sp,
+                                  LL * LL, RB, stride);
+    } else if (grid) {
+        hipExtLaunchKernelGGL((k_row_turn<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab, sp,
+                              stride, token);
     }
 }
 
@@ -166,23 +170,78 @@ void iter_pass_fn(int prec, int pass, bool grid, const PlanTabs& pt, const SlotD
         iter_pass_t<float>(pass, grid && G<float>::ROW_BLOCKS <= g4_blocks(), pt, slot, stride, token, e0, e1, s);
 }
 
-template <typename W>
-bool grid_capable_t() {
-    constexpr int RT = G<W>::ROW_THREADS, RB = G<W>::ROW_BLOCKS;
+// whether every workgroup of kernel `kern` (RB of RT threads) can be
+// resident at once on the current device
+template <int RT, int RB>
+bool whole_grid_resident(const void* kern) {
     if (RB > g4_blocks()) return false;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return false;
-    const auto kern = k_row_inv_upd<W, M, PAD, ByPtr, RT>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), RT, 0) !=
-        hipSuccess)
-        return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, RT, 0) != hipSuccess) return false;
     return (long)per_cu * cus >= RB;
+}
+
+template <typename W>
+bool grid_capable_t() {
+    constexpr int RT = G<W>::ROW_THREADS, RB = G<W>::ROW_BLOCKS;
+    return whole_grid_resident<RT, RB>(reinterpret_cast<const void*>(k_row_inv_upd<W, M, PAD, ByPtr, RT>));
 }
 
 bool grid_capable_fn(int prec) {
     return prec == 0 ? grid_capable_t<double>() : grid_capable_t<float>();
+}
+
+// The turn pass saves the reads of r and p and one launch per iteration but
+// adds a second barrier.  Measured against the folded update alone (whole
+// solves, alternating in one process): L = 2048 mixed +4.2%, L = 256 +2.2%,
+// L = 512 +0.5%, padded L = 512 FP64 +1.9%, but L = 1024 (this M = 2048
+// grid) -1.2%, so it is not offered there.
+constexpr bool kTurnPays = M != 2048;
+
+template <typename W>
+bool turn_capable_t() {
+    constexpr int RT = G<W>::ROW_THREADS, RB = G<W>::ROW_BLOCKS;
+    return kTurnPays && grid_capable_t<W>() &&
+           whole_grid_resident<RT, RB>(reinterpret_cast<const void*>(k_row_turn<W, M, PAD, ByPtr, RT>));
+}
+
+bool turn_capable_fn(int prec) {
+    return prec == 0 ? turn_capable_t<double>() : turn_capable_t<float>();
+}
+
+#ifndef FFTCG_TURN
+#define FFTCG_TURN 1
+#endif
+template <typename W>
+void iter_grid_chunk_t(const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long* token, int K,
+                       bool turn, hipStream_t s) {
+    if (!(turn && FFTCG_TURN)) {
+        for (int k = 0; k < K; ++k) iter_grid_t<W>(pt, slot, stride, ++*token, s);
+        return;
+    }
+    constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS, RB = G<W>::ROW_BLOCKS;
+    const ByPtr sp{slot};
+    const Tab<W> tab = tab_of<W>(pt);
+    hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProCG<W, W, RT>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, RB,
+                       stride);
+    hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
+    for (int k = 1; k < K; ++k) {
+        const unsigned long long t = *token + 1;
+        *token += 2;
+        hipLaunchKernelGGL((k_row_turn<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, t);
+        hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
+    }
+    hipLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, ++*token);
+}
+
+void iter_grid_chunk_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long* token,
+                        int K, bool turn, hipStream_t s) {
+    if (prec == 0)
+        iter_grid_chunk_t<double>(pt, slot, stride, token, K, turn, s);
+    else
+        iter_grid_chunk_t<float>(pt, slot, stride, token, K, turn, s);
 }
 
 void iter_fn(int prec, const PlanTabs& pt, const SlotDesc* slots, int nslots, int stride, hipStream_t s) {
@@ -332,7 +391,9 @@ const EngineOps kOps = {M,
                         &check0_pcg_fn,
                         &iter_grid_fn,
                         &iter_pass_fn,
-                        &grid_capable_fn};
+                        &grid_capable_fn,
+                        &iter_grid_chunk_fn,
+                        &turn_capable_fn};
 
 }  // namespace
 

@@ -264,6 +264,8 @@ extern "C" int fftcg_plan(int L, int padded, const double* kernel_spectrum, fftc
     if (p->ops) {
         p->grid_cap[0] = p->ops->grid_capable(FFTCG_FP64);
         p->grid_cap[1] = p->ops->grid_capable(FFTCG_MIXED);
+        p->turn_cap[0] = p->grid_cap[0] && p->ops->turn_capable(FFTCG_FP64);
+        p->turn_cap[1] = p->grid_cap[1] && p->ops->turn_capable(FFTCG_MIXED);
     }
     // quarter spectrum (host copy, FP64) for the fused engine
     p->quarter.resize((size_t)(M / 2 + 1) * (M / 2 + 1));
@@ -371,9 +373,15 @@ extern "C" int fftcg_plan_set_error_target(fftcg_plan_t plan, int precision, dou
     return FFTCG_OK;
 } FFTCG_ABI_CATCH
 
+// whether solves in `precision` on this plan use the turn pass (the folded
+// update's mode, and the turn pass's grid resident as a whole)
+static bool plan_turn(fftcg_plan_t plan, int precision) {
+    return (plan->grid_mode == 1 || plan->grid_mode == 2) && plan->turn_cap[precision == FFTCG_MIXED];
+}
+
 extern "C" int fftcg_plan_set_grid_sync(fftcg_plan_t plan, int mode) try {
     if (!plan) return FFTCG_EINVAL;
-    if (mode < 0 || mode > 2) return FFTCG_EINVAL;
+    if (mode < 0 || mode > 3) return FFTCG_EINVAL;
     std::lock_guard<std::mutex> lk(plan->mu);
     plan->grid_mode = mode;
     plan->grid_broken.store(0);
@@ -390,7 +398,7 @@ extern "C" int fftcg_plan_get_grid_sync(fftcg_plan_t plan, int precision, int* s
     else if (plan->grid_broken.load())
         *state = FFTCG_GRID_FELL_BACK;
     else
-        *state = FFTCG_GRID_ON;
+        *state = plan_turn(plan, precision) ? FFTCG_GRID_ON_TURN : FFTCG_GRID_ON;
     return FFTCG_OK;
 } FFTCG_ABI_CATCH
 
@@ -485,13 +493,26 @@ extern "C" int fftcg_profile_iteration(fftcg_plan_t plan, int precision, const d
     hipStream_t s = (hipStream_t)stream;
     const EngineOps* ops = plan->ops;
     const bool grid = plan->grid_mode != 0 && !plan->grid_broken.load() && plan->grid_cap[precision == FFTCG_MIXED];
+    const bool turn = grid && plan_turn(plan, precision);
+    if (turn && reps < 2) return FFTCG_EINVAL;
+    // the launches in the order a solve's chunk makes them: with the turn
+    // pass row_fwd, col, (turn, col) x (reps - 1), row_inv; else per
+    // iteration row_fwd, col, row_inv and (without the folded update) update
+    std::vector<int> seq;
+    if (turn) {
+        seq = {0, 1};
+        for (int k = 1; k < reps; ++k) seq.insert(seq.end(), {4, 1});
+        seq.push_back(2);
+    } else {
+        for (int k = 0; k < reps; ++k)
+            for (int pass = 0; pass < (grid ? 3 : 4); ++pass) seq.push_back(pass);
+    }
     Workspace* w = plan_acquire(plan);
     if (!w) return FFTCG_ENOMEM;
     int rc = FFTCG_OK;
     // a start and an end event per launch, recorded by the launch itself
     // (the kernel's own execution, as a kernel trace reports it)
-    const int npass = grid ? 3 : 4;
-    std::vector<hipEvent_t> ev((size_t)2 * npass * reps, nullptr);
+    std::vector<hipEvent_t> ev((size_t)2 * seq.size(), nullptr);
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             e = nullptr;
@@ -520,12 +541,18 @@ extern "C" int fftcg_profile_iteration(fftcg_plan_t plan, int precision, const d
             break;
         }
         ops->check0(precision, plan->tabs, w->slot, 1, plan->stride, s);
-        for (int k = 0; k < reps; ++k)
-            for (int pass = 0; pass < npass; ++pass) {
-                const unsigned long long token = (grid && pass == 2) ? ++w->grid_token : 0;
-                const size_t e = 2 * ((size_t)k * npass + pass);
-                ops->iter_pass(precision, pass, grid, plan->tabs, w->slot, plan->stride, token, ev[e], ev[e + 1], s);
+        for (size_t i = 0; i < seq.size(); ++i) {
+            const int pass = seq[i];
+            unsigned long long token = 0;
+            if (grid && pass == 2) {
+                token = ++w->grid_token;
+            } else if (pass == 4) {
+                token = w->grid_token + 1;
+                w->grid_token += 2;
             }
+            ops->iter_pass(precision, pass, grid, plan->tabs, w->slot, plan->stride, token, ev[2 * i], ev[2 * i + 1],
+                           s);
+        }
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(w->h_state, w->st, sizeof(SolveState), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
@@ -542,16 +569,18 @@ extern "C" int fftcg_profile_iteration(fftcg_plan_t plan, int precision, const d
             rc = (st.done && st.status < 0) ? st.status : FFTCG_EINVAL;
             break;
         }
-        double acc[4] = {0, 0, 0, 0};
-        for (int k = 0; k < reps; ++k)
-            for (int pass = 0; pass < npass; ++pass) {
-                const size_t e = 2 * ((size_t)k * npass + pass);
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, ev[e], ev[e + 1]);
-                acc[pass] += ms;
-            }
-        for (int pass = 0; pass < 4; ++pass) ms_per_pass[pass] = acc[pass] / reps;
-        if (folded) *folded = grid ? 1 : 0;
+        double acc[5] = {0, 0, 0, 0, 0};
+        int cnt[5] = {0, 0, 0, 0, 0};
+        for (size_t i = 0; i < seq.size(); ++i) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+            acc[seq[i]] += ms;
+            cnt[seq[i]] += 1;
+        }
+        // (the separate update launches nothing when the update is folded)
+        for (int pass = 0; pass < 5; ++pass)
+            ms_per_pass[pass] = (cnt[pass] > 0 && !(grid && pass == 3)) ? acc[pass] / cnt[pass] : 0.0;
+        if (folded) *folded = turn ? 2 : (grid ? 1 : 0);
     } while (0);
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -805,12 +834,11 @@ static int solve_multipass_once(fftcg_plan_t plan, Workspace* w, int precision, 
         bool finished = false;
         while (!finished) {
             const int K = planner.next();
-            for (int k = 0; k < K; ++k) {
-                if (grid)
-                    grid = ops->iter_grid(precision, plan->tabs, w->slot, plan->stride, ++w->grid_token, s);
-                else
-                    iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
-            }
+            if (grid)
+                ops->iter_grid_chunk(precision, plan->tabs, w->slot, plan->stride, &w->grid_token, K,
+                                     plan_turn(plan, precision), s);
+            else
+                for (int k = 0; k < K; ++k) iter(precision, plan->tabs, w->slot, 1, plan->stride, s);
             check(precision, plan->tabs, w->slot, 1, plan->stride, s);
             if (hipGetLastError() != hipSuccess || hipEventRecord(w->ev[c & 1], s) != hipSuccess) {
                 rc = FFTCG_EDEVICE;

@@ -110,6 +110,7 @@ struct fftcg_plan_s {
     // separate update kernel until the mode is set again)
     int grid_mode = 1;
     bool grid_cap[2] = {false, false};
+    bool turn_cap[2] = {false, false};  // the turn pass (k_row_turn) resident as a whole, per precision
     std::atomic<int> grid_broken{0};
     std::mutex mu;
     std::vector<fftcg::Workspace*> free_ws;

@@ -112,8 +112,9 @@ __device__ __forceinline__ void publish_status(const SlotDesc& sd, int done, int
 // working-precision recursion may drift from the true residual).  The last
 // two need an iteration since the previous check, so checks alternate with
 // progress.
-__device__ __forceinline__ bool check_due(const SolveState* st, double rr) {
-    const int iters = st->iters;
+// iters: the iteration count the decision is for (st->iters, unless the
+// caller has counted an iteration whose store to st it cannot read back)
+__device__ __forceinline__ bool check_due(const SolveState* st, double rr, int iters) {
     const bool progressed = iters > st->last_check_iter;
     const bool periodic = st->refresh > 0 && iters - st->last_check_iter >= st->refresh;
     const bool candidate = progressed && !(rr > st->trigger_rr);
@@ -124,6 +125,7 @@ __device__ __forceinline__ bool check_due(const SolveState* st, double rr) {
     const bool reliable = progressed && rr <= rel && st->trigger_rr < 1e-2 * rel;
     return iters >= st->maxit || candidate || periodic || reliable;
 }
+__device__ __forceinline__ bool check_due(const SolveState* st, double rr) { return check_due(st, rr, st->iters); }
 
 // Outcome of an FP64 check from its reductions: |b - A x|^2 (R), |x|^2 (X),
 // |b|^2 (B), |r_working|^2 (RW), invalid-input count (BAD), drift of the
@@ -912,6 +914,48 @@ struct EpiPreT<Epi, true> {
 
 // ==== kernels ==============================================================
 
+// The forward row transform of the thread's inputs v (the row's packed
+// values, as the prologue placed them), the split of the packed transform
+// into the half spectrum of the real row, and the W stores of the
+// workgroup's rows (block rb).
+template <typename T, int M, int PAD, int NT>
+__device__ __forceinline__ void row_fwd_out(cx<T>* v, cx<T>* lds, const Tab<T>& tab, const SlotDesc& sd, int rb) {
+    using G = Geo<T, M, PAD>;
+    constexpr int N = G::N, E = G::ER, P = G::PR, RPW = G::RPW, L = G::L, TT = G::TT;
+    constexpr int WORDS = G::ROW_WORDS;
+    const int tid = threadIdx.x;
+    const int rl = tid / P, j = tid % P;
+    LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
+    constexpr int NSTG = fft_nstages(N);
+    fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
+    constexpr int RL = NSTG > 0 ? fft_radix(N, false, NSTG - 1) : 1;
+    if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
+#pragma unroll
+    for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, N / RL>(j + u * P, v + u * RL);
+    __syncthreads();
+    cx<T>* Wb = reinterpret_cast<cx<T>*>(sd.W);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int qi = tid + s * NT;
+        const int kk = qi % TT;
+        const int il = (qi / TT) % RPW;
+        const int kt = qi / (TT * RPW);
+        const int k = kt * TT + kk;
+        LdsLay<T, 1, 4, 1> rl2{lds + il * WORDS, 0};
+        const cx<T> Zk = rl2.ld(k);
+        cx<T> out;
+        if (k == 0) {
+            out = mkc(Zk.x + Zk.y, Zk.x - Zk.y);
+        } else {
+            const cx<T> B = conjc(rl2.ld(N - k));
+            const cx<T> s1 = Zk + B, d1 = Zk - B;
+            const cx<T> wd = cmul(tab.tw[k], d1);
+            out = mkc(T(0.5) * (s1.x + wd.y), T(0.5) * (s1.y - wd.x));
+        }
+        gst(Wb + ((size_t)kt * L + rb * RPW + il) * TT + kk, out);
+    }
+}
+
 template <typename T, int M, int PAD, class Pro, class Slot, int NT>
 __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart_rr, int stride) {
     using G = Geo<T, M, PAD>;
@@ -927,7 +971,6 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
     const int rl = tid / P, j = tid % P;
     const int rb = xcd_remap(blockIdx.x, gridDim.x);
     const int row = rb * RPW + rl;
-    LdsLay<T, 1, 4, 1> lay{lds + rl * WORDS, 0};
     cx<T> v[E];
     constexpr int NSTG = fft_nstages(N);
     constexpr int R1 = NSTG > 0 ? fft_radix(N, false, 0) : 1;
@@ -962,33 +1005,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart
             for (int r = 0; r < RK; ++r)
                 v[u * R1 + r] = Pro::template load2<L>(sd, sh, row, 2 * ((j + u * P) + r * (N / R1)), &acc);
     }
-    fft_run<T, N, M, -1, false, PAD != 0>(v, lay, j, tab.tw);
-    constexpr int RL = NSTG > 0 ? fft_radix(N, false, NSTG - 1) : 1;
-    if constexpr (NSTG > 1) __syncthreads();  // the transform's last reads before these writes
-#pragma unroll
-    for (int u = 0; u < E / RL; ++u) lay.template st_run<RL, N / RL>(j + u * P, v + u * RL);
-    __syncthreads();
-    cx<T>* Wb = reinterpret_cast<cx<T>*>(sd.W);
-#pragma unroll
-    for (int s = 0; s < E; ++s) {
-        const int qi = tid + s * NT;
-        const int kk = qi % TT;
-        const int il = (qi / TT) % RPW;
-        const int kt = qi / (TT * RPW);
-        const int k = kt * TT + kk;
-        LdsLay<T, 1, 4, 1> rl2{lds + il * WORDS, 0};
-        const cx<T> Zk = rl2.ld(k);
-        cx<T> out;
-        if (k == 0) {
-            out = mkc(Zk.x + Zk.y, Zk.x - Zk.y);
-        } else {
-            const cx<T> B = conjc(rl2.ld(N - k));
-            const cx<T> s1 = Zk + B, d1 = Zk - B;
-            const cx<T> wd = cmul(tab.tw[k], d1);
-            out = mkc(T(0.5) * (s1.x + wd.y), T(0.5) * (s1.y - wd.x));
-        }
-        gst(Wb + ((size_t)kt * L + rb * RPW + il) * TT + kk, out);
-    }
+    row_fwd_out<T, M, PAD, NT>(v, lds, tab, sd, rb);
     if constexpr (LATE && Pro::PREF && (E / R1) * RK <= 8) {
 #pragma unroll
         for (int u = 0; u < E / R1; ++u)
@@ -1112,7 +1129,9 @@ __global__ void __launch_bounds__(NT) k_col(Tab<T> tab, Slot slot) {
 
 // Body of the row-inverse pass; token: the grid-wide barrier's arrival
 // token of this launch (epilogues with the folded update only).
-template <typename T, int M, int PAD, class Epi, class Slot, int NT>
+// FWD (with the folded update only): the pass goes on into the next
+// iteration's forward row pass on the same rows (k_row_turn).
+template <typename T, int M, int PAD, class Epi, class Slot, int NT, bool FWD = false>
 __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot, int stride,
                                              unsigned long long token) {
     using G = Geo<T, M, PAD>;
@@ -1126,6 +1145,10 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
     const int tid = threadIdx.x;
     const int rl = tid / P, j = tid % P;
     const int row0 = xcd_remap(blockIdx.x, gridDim.x) * RPW;
+    // FWD: the iteration count as this launch found it (block 0 advances
+    // st->iters after the first barrier; read before this workgroup arrives)
+    __shared__ int s_iters;
+    if (FWD && tid == 0) s_iters = sd.st->iters;
     const cx<T>* Wb = reinterpret_cast<const cx<T>*>(sd.W);
     // all of this thread's spectrum values are requested before the first
     // is stored to LDS (more reads in flight per wave)
@@ -1150,10 +1173,14 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
     constexpr int RL = NSTG > 0 ? fft_radix(N, true, NSTG - 1) : 1;
     constexpr int RK = (PAD && RL > 1) ? RL / 2 : RL;  // outputs kept per run (the rest are cropped)
     const int row = row0 + rl;
-    // the epilogue's operands (Epi::PREF), requested with the spectrum
+    // the epilogue's operands (Epi::PREF), requested with the spectrum; not
+    // in the turn pass (FWD) on the largest rows (16 pairs a thread), which
+    // keeps p of the pairs to its end and would otherwise exceed 128 VGPRs
+    // (four workgroups per CU)
+    constexpr bool PF = Epi::PREF && !(FWD && E >= 16);
     using PreT = typename EpiPreT<Epi>::type;
-    PreT pre[Epi::PREF ? (E / RL) * RK : 1];
-    if constexpr (Epi::PREF) {
+    PreT pre[PF ? (E / RL) * RK : 1];
+    if constexpr (PF) {
 #pragma unroll
         for (int u = 0; u < E / RL; ++u)
 #pragma unroll
@@ -1205,19 +1232,22 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
     constexpr bool UPD = EpiUpd<Epi>::value;
     constexpr int NO = (E / RL) * RK;  // outputs (pairs) of this thread
     cx<T> qk[UPD ? NO : 1], rk[UPD ? NO : 1];
+    static_assert(!FWD || UPD, "the fused forward pass follows the folded update");
+    cx<T> pk[FWD ? NO : 1];  // FWD: p of the pairs, for the next direction and the x update
 #pragma unroll
     for (int u = 0; u < E / RL; ++u)
 #pragma unroll
         for (int r = 0; r < RK; ++r) {
             const int n = (j + u * P) + r * (N / RL);
             if constexpr (UPD) {
-                // FP32 prefetched p and d with the spectrum; FP64 reads them here
+                // p and d prefetched with the spectrum (PF), or read here
                 typename Epi::Pre pr;
-                if constexpr (Epi::PREF)
+                if constexpr (PF)
                     pr = pre[u * RK + r];
                 else
                     pr = Epi::template pre<L>(sd, row, 2 * n);
                 qk[u * RK + r] = Epi::template outq<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, pr, acc);
+                if constexpr (FWD) pk[u * RK + r] = pr.p;
             } else if constexpr (Epi::PREF) {
                 Epi::template out2p<L>(sd, row, 2 * n, v[u * RL + r].x, v[u * RL + r].y, pre[u * RK + r], acc);
             } else {
@@ -1266,16 +1296,18 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0);
         }
-        const bool ok = grid_barrier<NT>(reinterpret_cast<unsigned long long*>(sd.part + PS_BAR * stride), bar_rel,
-                                         token, st->bar_limit);
-        if (!ok) {
-            // the grid was not resident as a whole: the solve is abandoned
-            // and the host repeats it with the separate update kernel
+        auto* bar_flags = reinterpret_cast<unsigned long long*>(sd.part + PS_BAR * stride);
+        // the grid was not resident as a whole: the solve is abandoned and
+        // the host repeats it with the separate update kernel
+        auto give_up = [&]() {
             if (tid == 0) {
                 __hip_atomic_store(&st->status, ST_EGRID, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 publish_status(sd, 1, ST_EGRID, st->gen, st->iters, st->last_check_iter);
             }
+        };
+        if (!grid_barrier<NT>(bar_flags, bar_rel, token, st->bar_limit)) {
+            give_up();
             return;
         }
         // every partial: strided per thread, then the block sum (the update
@@ -1312,9 +1344,73 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
                 rv.y -= a * qv.y;
                 st2<T>(reinterpret_cast<T*>(sd.r) + (size_t)row * L + 2 * ((j + u * P) + r * (N / RL)), rv);
                 rr += (double)rv.x * rv.x + (double)rv.y * rv.y;
+                if constexpr (FWD) rk[u * RK + r] = rv;
             }
         const double srr = block_sum<NT>(rr, red);
-        if (tid == 0) sd.part[PS_RR * stride + blockIdx.x] = srr;
+        if constexpr (!FWD) {
+            if (tid == 0) sd.part[PS_RR * stride + blockIdx.x] = srr;
+        } else {
+            // The next iteration's forward row pass on the same rows, as
+            // ProCG in k_row_fwd computes it: beta = r.r / rho from every
+            // workgroup's r.r partial (a second barrier, token + 1; the same
+            // summation order), the check decision, p <- r + beta p, the
+            // transform, and the pending x update x <- x + alpha p_old.  The
+            // forward pass's first radix equals this pass's last, so the
+            // thread holds the same pairs of r and p in both.
+            auto* rr_bits = reinterpret_cast<unsigned long long*>(sd.part + PS_RR * stride);
+            if (tid == 0) {
+                (void)__hip_atomic_exchange(rr_bits + blockIdx.x, __builtin_bit_cast(unsigned long long, srr),
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+            }
+            if (!grid_barrier<NT>(bar_flags, bar_rel, token + 1, st->bar_limit)) {
+                give_up();
+                return;
+            }
+            double s2 = 0.0;
+            for (int i = tid; i < (int)gridDim.x; i += NT)
+                s2 += __builtin_bit_cast(double, __hip_atomic_load(rr_bits + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            const double rrn = block_sum<NT>(s2, red);
+            if (check_due(st, rrn, s_iters + 1)) {
+                if (blockIdx.x == 0 && tid == 0) st->pause = 1;
+                return;
+            }
+            if (blockIdx.x == 0 && tid == 0) st->rho_cur = rrn;
+            const T beta = (T)(rrn / rho);
+            constexpr int R1 = NSTG > 0 ? fft_radix(N, false, 0) : 1;
+            static_assert(R1 == RL, "forward first radix and inverse last radix");
+            cx<T> v2[E];
+#pragma unroll
+            for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+                for (int r = 0; r < RK; ++r) {
+                    const cx<T> rv = rk[u * RK + r], po = pk[u * RK + r];
+                    const cx<T> p2 = mkc(rv.x + beta * po.x, rv.y + beta * po.y);
+                    st2<T>(reinterpret_cast<T*>(sd.p) + (size_t)row * L + 2 * ((j + u * P) + r * (N / RL)), p2);
+                    v2[u * RL + r] = p2;
+                }
+            if (a != T(0)) {
+                T* xa = reinterpret_cast<T*>(sizeof(T) == 8 ? (void*)sd.x : (void*)sd.e);
+#pragma unroll
+                for (int u = 0; u < E / RL; ++u)
+#pragma unroll
+                    for (int r = 0; r < RK; ++r) {
+                        T* xp = xa + (size_t)row * L + 2 * ((j + u * P) + r * (N / RL));
+                        cx<T> xv = ld2<T>(xp);
+                        xv.x += a * pk[u * RK + r].x;
+                        xv.y += a * pk[u * RK + r].y;
+                        st2<T>(xp, xv);
+                    }
+            }
+            // the table pointer is laundered so that the compiler reloads the
+            // forward transform's twiddles instead of keeping the inverse
+            // half's loads of the same entries live across both barriers
+            // (163 instead of 118 VGPRs: three workgroups per CU, and the
+            // grid would not be resident as a whole)
+            Tab<T> tab2 = tab;
+            asm volatile("" : "+s"(tab2.tw));
+            row_fwd_out<T, M, PAD, NT>(v2, lds, tab2, sd, __builtin_amdgcn_readfirstlane(row0 / RPW));
+        }
     }
 }
 
@@ -1329,6 +1425,15 @@ __global__ void __launch_bounds__(NT) k_row_inv(Tab<T> tab, Slot slot, int strid
 template <typename T, int M, int PAD, class Slot, int NT>
 __global__ void __launch_bounds__(NT) k_row_inv_upd(Tab<T> tab, Slot slot, int stride, unsigned long long token) {
     row_inv_body<T, M, PAD, EpiCGU<T>, Slot, NT>(tab, slot, stride, token);
+}
+
+// One CG iteration's turn in one pass (k_row_inv_upd followed by k_row_fwd):
+// q's row inverse, the folded update, and the next direction's forward row
+// transform, with two grid-wide barriers (tokens token and token + 1).
+template <typename T, int M, int PAD, class Slot, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_row_turn(Tab<T> tab, Slot slot, int stride, unsigned long long token) {
+    row_inv_body<T, M, PAD, EpiCGU<T>, Slot, NT, true>(tab, slot, stride, token);
 }
 
 // r <- r - alpha q, partial r . r.  alpha = rho / (p . q) from the partials

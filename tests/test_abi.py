@@ -130,7 +130,7 @@ def test_new_calls_reject_null(lib):
     assert lib.fftcg_plan_set_grid_sync(None, 1) == binding.EINVAL
     assert lib.fftcg_server_reserve(None, P(1), binding.MIXED, 4) == binding.EINVAL
     assert lib.fftcg_server_class_slots(None, P(1), binding.MIXED, ctypes.byref(idx)) == binding.EINVAL
-    ms = (ctypes.c_double * 4)()
+    ms = (ctypes.c_double * 5)()
     assert lib.fftcg_profile_iteration(None, binding.MIXED, P(1), P(2), P(3), 10, ms, None, None) == binding.EINVAL
     st = ctypes.c_int(-1)
     assert lib.fftcg_plan_get_grid_sync(None, binding.MIXED, ctypes.byref(st)) == binding.EINVAL

@@ -49,7 +49,8 @@ def test_kernel_hash_follows_code_and_flags(tmp_path, monkeypatch):
 def test_byte_model_of_the_iteration():
     """Per pass at L = 2048 (M = 4096, N = 2048 packed columns): the folded
     iteration moves 8 L^2 bytes less than the separate one (q is neither
-    written nor read; r is read and written by the row-inverse pass)."""
+    written nor read; r is read and written by the row-inverse pass), and
+    the turn pass 8 L^2 less again."""
     L, M = 2048, 4096
     bm = bench.bytes_model(L, M)
     n, W = L * L, 8 * L * (M // 2)
@@ -60,5 +61,9 @@ def test_byte_model_of_the_iteration():
     assert bm["iteration_folded"] == ps["row_fwd"] + ps["col"] + ps["row_inv_upd"]
     assert bm["iteration"] - bm["iteration_folded"] == 8 * n
     assert round(bm["iteration_folded"] / 1e6, 1) == 302.0
+    # the turn pass: row_inv_upd then row_fwd on the same rows, without
+    # reading back r (written by the first half) and p (held from it)
+    assert ps["turn"] == ps["row_inv_upd"] + ps["row_fwd"] - 8 * n
+    assert bm["iteration_turn"] == ps["col"] + ps["turn"] == bm["iteration_folded"] - 8 * n
     names = bench.pass_kernels(M)
     assert set(names) == set(ps)

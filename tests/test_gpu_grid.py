@@ -18,7 +18,10 @@ differently, so solutions agree to within the solves' tolerance, not bitwise.
   warm start given in place (x0 == x);
 * the masked operator of the fracture driver (Sec. 2) through the folded
   path at L = 512, breaks replayed by the oracle;
-* repeatability, a busy device, and the iteration timing aid.
+* repeatability, a busy device, and the iteration timing aid;
+* the turn pass (the row-inverse pass going on into the next iteration's
+  forward row pass, mode 1 where it fits) against the folded update alone
+  (mode 3): the same arithmetic in the same order, so bitwise the same.
 """
 
 import json
@@ -35,6 +38,7 @@ from gpu_util import dev, host, relerr, banner
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ON = (binding.GRID_ON, binding.GRID_ON_TURN)  # the folded update, with or without the turn pass
 
 
 def _solve(plan, inst, mode, x0=None, tol=1e-8):
@@ -51,14 +55,17 @@ def test_grid_sync_states():
     L = 2048
     plan = binding.Plan(L, 1, spectrum(2 * L, 1e-4))
     banner("grid-states", L)
-    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    # the turn pass fits in 128 VGPRs: four workgroups per CU, the whole grid
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON_TURN
     # FP64 at M = 4096: 2 workgroups of the pass per CU, fewer than it has
-    assert plan.grid_sync(binding.FP64) in (binding.GRID_UNSUPPORTED, binding.GRID_ON)
+    assert plan.grid_sync(binding.FP64) in (binding.GRID_UNSUPPORTED,) + ON
     plan.set_grid_sync(0)
     assert plan.grid_sync(binding.MIXED) == binding.GRID_OFF
-    plan.set_grid_sync(1)
+    plan.set_grid_sync(3)
     assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
-    for bad in (-1, 3):
+    plan.set_grid_sync(1)
+    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON_TURN
+    for bad in (-1, 4):
         with pytest.raises(binding.FftcgError):
             plan.set_grid_sync(bad)
     plan.close()
@@ -82,7 +89,7 @@ def test_grid_full_size_against_oracle_samples(s):
         assert gap <= (1e-8 + g["bound"]) * g["xnorm"], (mode, gap)
         xs[mode] = (x, info)
         # mode 1 ran folded throughout (no barrier gave up)
-        assert plan.grid_sync(binding.MIXED) == (binding.GRID_ON if mode == 1 else binding.GRID_OFF)
+        assert plan.grid_sync(binding.MIXED) == (binding.GRID_ON_TURN if mode == 1 else binding.GRID_OFF)
     assert abs(xs[1][1]["iterations"] - xs[0][1]["iterations"]) <= 2
     assert relerr(xs[1][0], xs[0][0]) <= 2e-8
     plan.close()
@@ -94,7 +101,7 @@ def test_grid_L256_against_oracle():
     xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 1)
     plan = binding.Plan(L, 1, inst["ghat"])
     banner("grid-L256", L)
-    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    assert plan.grid_sync(binding.MIXED) in ON
     for mode in (1, 0):
         x, info = _solve(plan, inst, mode)
         err = relerr(x, xr)
@@ -113,7 +120,7 @@ def test_grid_fp64_against_oracle(L):
     xr, rinfo = reference_solve(inst["ghat"], inst["d"], inst["b"], 1)
     plan = binding.Plan(L, 1, inst["ghat"])
     banner("grid-fp64", L)
-    assert plan.grid_sync(binding.FP64) == binding.GRID_ON
+    assert plan.grid_sync(binding.FP64) in ON
     for mode in (1, 0):
         plan.set_grid_sync(mode)
         x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
@@ -128,6 +135,7 @@ def test_grid_fp64_against_oracle(L):
     ms, folded = plan.profile_iteration(dev(inst["d"]), dev(inst["b"]), torch.empty_like(x), reps=8,
                                         precision=binding.FP64)
     assert folded and ms[3] == 0.0 and all(v > 0 for v in ms[:3])
+    assert (ms[4] > 0) == (folded == 2)
     plan.close()
 
 
@@ -144,7 +152,7 @@ def test_grid_fallback_repeats_solve():
     assert np.array_equal(x2, x0) and info2["iterations"] == info0["iterations"]
     # setting a mode again takes the folded path up again
     plan.set_grid_sync(1)
-    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    assert plan.grid_sync(binding.MIXED) in ON
     x1, info1 = _solve(plan, inst, 1)
     assert info1["status"] == binding.OK and relerr(x1, x0) <= 2e-8
     plan.close()
@@ -180,13 +188,13 @@ def test_grid_fracture_masked_L512():
     inst = fracture_instance(0, L=L)
     gh = spectrum(2 * L, 1e-3)
     plan = binding.Plan(L, 1, gh)
-    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    assert plan.grid_sync(binding.MIXED) in ON
     f = torch.zeros((L, L), dtype=torch.float64, device="cuda")
     banner("grid-fracture-L512", steps)
     st, broken, dbreak, iters = plan.fracture(inst["k"], dev(inst["t"]), f, steps, tol=tol,
                                               precision=binding.MIXED)
     assert st == binding.OK
-    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    assert plan.grid_sync(binding.MIXED) in ON
     _, fo_dbreak, fo_f, ratios = fracture_sequence(gh, inst["k"], inst["t"], steps, 1, replay=broken)
     t = inst["t"].ravel()
     for s in range(steps):
@@ -213,7 +221,7 @@ def test_grid_repeatable():
     xa, ia = _solve(plan, inst, 1)
     xb, ib = _solve(plan, inst, 1)
     assert ia["status"] == binding.OK and ib["status"] == binding.OK
-    assert plan.grid_sync(binding.MIXED) == binding.GRID_ON
+    assert plan.grid_sync(binding.MIXED) in ON
     assert np.array_equal(xa, xb) and ia["iterations"] == ib["iterations"]
     plan.close()
 
@@ -244,7 +252,7 @@ def test_grid_with_other_stream_busy():
     print(f"state {state}, iters {info['iterations']} (separate {i0['iterations']}), "
           f"bound {info['error_bound']:.3e}, checksum {float(c[0, 0]):.3e}")
     assert info["status"] == binding.OK and info["error_bound"] <= 1e-8
-    assert state in (binding.GRID_ON, binding.GRID_FELL_BACK)
+    assert state in ON + (binding.GRID_FELL_BACK,)
     assert relerr(host(x), x0) <= 2e-8
     plan.close()
 
@@ -263,12 +271,20 @@ def test_profile_iteration(L):
     ms, folded = plan.profile_iteration(d, b, x, reps=40)
     print(f"folded: {folded}, ms {[round(v, 4) for v in ms]}")
     assert folded and all(v > 0 for v in ms[:3]) and ms[3] == 0.0
+    assert (folded == 2) == (plan.grid_sync(binding.MIXED) == binding.GRID_ON_TURN) == (ms[4] > 0)
+    if folded == 2:
+        with pytest.raises(binding.FftcgError):  # the turn pass needs two iterations
+            plan.profile_iteration(d, b, x, reps=1)
+    plan.set_grid_sync(3)
+    ms3, folded3 = plan.profile_iteration(d, b, x, reps=40)
+    print(f"folded, no turn: ms {[round(v, 4) for v in ms3]}")
+    assert folded3 == 1 and all(v > 0 for v in ms3[:3]) and ms3[3] == 0.0 and ms3[4] == 0.0
     plan.set_grid_sync(0)
     ms0, folded0 = plan.profile_iteration(d, b, x, reps=40)
     print(f"separate: ms {[round(v, 4) for v in ms0]}")
-    assert not folded0 and all(v > 0 for v in ms0)
+    assert not folded0 and all(v > 0 for v in ms0[:4]) and ms0[4] == 0.0
     ms64, _ = plan.profile_iteration(d, b, x, reps=4, precision=binding.FP64)
-    assert all(v > 0 for v in ms64)
+    assert all(v > 0 for v in ms64[:4])
     with pytest.raises(binding.FftcgError):
         plan.profile_iteration(d, torch.zeros_like(b), x, reps=4)
     with pytest.raises(binding.FftcgError):
@@ -309,8 +325,38 @@ def test_grid_two_solves_concurrently():
     torch.cuda.synchronize()
     state = plan.grid_sync(binding.MIXED)
     print(f"state {state}, iters {[i['iterations'] for i in infos]}")
-    assert state in (binding.GRID_ON, binding.GRID_FELL_BACK)
+    assert state in ON + (binding.GRID_FELL_BACK,)
     for k in (0, 1):
         assert infos[k]["status"] == binding.OK and infos[k]["error_bound"] <= 1e-8
         assert relerr(host(X[k]), ref[k]) <= 2e-8
+    plan.close()
+
+
+@pytest.mark.parametrize("L,precision,tol", [(2048, binding.MIXED, 1e-8), (256, binding.MIXED, 1e-8),
+                                             (512, binding.FP64, 1e-10)])
+def test_turn_pass_bitwise_as_folded(L, precision, tol):
+    """Mode 1 (the turn pass, where it fits) against mode 3 (the folded
+    update and the forward row pass as separate launches): beta from the
+    same r.r partials in the same order, p <- r + beta p and the x update
+    with the same operations, so the solutions, iteration counts and error
+    bounds are bitwise equal."""
+    import torch
+    inst = c3_instance(0) if L == 2048 else padded_instance(L, [3, 13, L], eps=1e-4, normal_b=True)
+    plan = binding.Plan(L, 1, inst["ghat"])
+    banner("turn-vs-folded", L, precision)
+    out = {}
+    for mode in (3, 1):
+        plan.set_grid_sync(mode)
+        state = plan.grid_sync(precision)
+        x = torch.zeros((L, L), dtype=torch.float64, device="cuda")
+        info = plan.solve(dev(inst["d"]), dev(inst["b"]), x, tol=tol, precision=precision)
+        out[mode] = (host(x), info, state)
+        print(f"mode {mode}: state {state} iters {info['iterations']} bound {info['error_bound']:.3e}")
+    assert out[3][2] == binding.GRID_ON
+    if L == 2048:
+        assert out[1][2] == binding.GRID_ON_TURN
+    assert out[1][2] in ON
+    assert out[1][1]["iterations"] == out[3][1]["iterations"]
+    assert out[1][1]["error_bound"] == out[3][1]["error_bound"]
+    assert np.array_equal(out[1][0], out[3][0])
     plan.close()
