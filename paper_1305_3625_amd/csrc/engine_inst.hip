@@ -132,6 +132,17 @@ bool iter_grid_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride
     return true;
 }
 
+// The turn pass saves the reads of r and p and one launch per iteration but
+// adds a second barrier.  Measured against the folded update alone (whole
+// solves, alternating in one process): L = 2048 mixed +4.2%, L = 256 +2.2%,
+// L = 512 +0.5%, padded L = 512 FP64 +1.9%, but L = 1024 (this M = 2048
+// grid) -1.2%, so it is not offered there.
+constexpr bool kTurnPays = M != 2048;
+// Built where its grid can be resident at once: not in FP64 on rows of 16
+// pairs a thread and more (over 200 VGPRs, two workgroups per CU).
+template <typename W>
+constexpr bool kTurnBuilt = !(sizeof(W) == 8 && G<W>::ER >= 16);
+
 template <typename W>
 void iter_pass_t(int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long token,
                  hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
@@ -156,9 +167,10 @@ void iter_pass_t(int pass, bool grid, const PlanTabs& pt, const SlotDesc* slot, 
         if (!grid)
             hipExtLaunchKernelGGL((k_update<W, UPD_NT>), dim3(g4_blocks()), dim3(UPD_NT), 0, s, e0, e1, 0, sp,
                                   LL * LL, RB, stride);
-    } else if (grid) {
-        hipExtLaunchKernelGGL((k_row_turn<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab, sp,
-                              stride, token);
+    } else if constexpr (kTurnBuilt<W>) {
+        if (grid)
+            hipExtLaunchKernelGGL((k_row_turn<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, e0, e1, 0, tab, sp,
+                                  stride, token);
     }
 }
 
@@ -193,47 +205,44 @@ bool grid_capable_fn(int prec) {
     return prec == 0 ? grid_capable_t<double>() : grid_capable_t<float>();
 }
 
-// The turn pass saves the reads of r and p and one launch per iteration but
-// adds a second barrier.  Measured against the folded update alone (whole
-// solves, alternating in one process): L = 2048 mixed +4.2%, L = 256 +2.2%,
-// L = 512 +0.5%, padded L = 512 FP64 +1.9%, but L = 1024 (this M = 2048
-// grid) -1.2%, so it is not offered there.
-constexpr bool kTurnPays = M != 2048;
-
 template <typename W>
 bool turn_capable_t() {
     constexpr int RT = G<W>::ROW_THREADS, RB = G<W>::ROW_BLOCKS;
-    return kTurnPays && grid_capable_t<W>() &&
-           whole_grid_resident<RT, RB>(reinterpret_cast<const void*>(k_row_turn<W, M, PAD, ByPtr, RT>));
+    if constexpr (!kTurnBuilt<W>)
+        return false;
+    else
+        return kTurnPays && grid_capable_t<W>() &&
+               whole_grid_resident<RT, RB>(reinterpret_cast<const void*>(k_row_turn<W, M, PAD, ByPtr, RT>));
 }
 
 bool turn_capable_fn(int prec) {
     return prec == 0 ? turn_capable_t<double>() : turn_capable_t<float>();
 }
 
-#ifndef FFTCG_TURN
-#define FFTCG_TURN 1
-#endif
 template <typename W>
 void iter_grid_chunk_t(const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long* token, int K,
                        bool turn, hipStream_t s) {
-    if (!(turn && FFTCG_TURN)) {
-        for (int k = 0; k < K; ++k) iter_grid_t<W>(pt, slot, stride, ++*token, s);
-        return;
+    if constexpr (kTurnBuilt<W>) {
+        if (turn) {
+            constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS, RB = G<W>::ROW_BLOCKS;
+            const ByPtr sp{slot};
+            const Tab<W> tab = tab_of<W>(pt);
+            hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProCG<W, W, RT>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab,
+                               sp, RB, stride);
+            hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
+            for (int k = 1; k < K; ++k) {
+                const unsigned long long t = *token + 1;
+                *token += 2;
+                hipLaunchKernelGGL((k_row_turn<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, t);
+                hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab,
+                                   sp);
+            }
+            hipLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride,
+                               ++*token);
+            return;
+        }
     }
-    constexpr int RT = G<W>::ROW_THREADS, CT = G<W>::COL_THREADS, RB = G<W>::ROW_BLOCKS;
-    const ByPtr sp{slot};
-    const Tab<W> tab = tab_of<W>(pt);
-    hipLaunchKernelGGL((k_row_fwd<W, M, PAD, ProCG<W, W, RT>, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, RB,
-                       stride);
-    hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
-    for (int k = 1; k < K; ++k) {
-        const unsigned long long t = *token + 1;
-        *token += 2;
-        hipLaunchKernelGGL((k_row_turn<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, t);
-        hipLaunchKernelGGL((k_col<W, M, PAD, GateIter, ByPtr, CT>), dim3(G<W>::NTILE), dim3(CT), 0, s, tab, sp);
-    }
-    hipLaunchKernelGGL((k_row_inv_upd<W, M, PAD, ByPtr, RT>), dim3(RB), dim3(RT), 0, s, tab, sp, stride, ++*token);
+    for (int k = 0; k < K; ++k) iter_grid_t<W>(pt, slot, stride, ++*token, s);
 }
 
 void iter_grid_chunk_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride, unsigned long long* token,

@@ -959,7 +959,7 @@ __device__ __forceinline__ void row_fwd_out(cx<T>* v, cx<T>* lds, const Tab<T>& 
 template <typename T, int M, int PAD, class Pro, class Slot, int NT>
 __global__ void __launch_bounds__(NT) k_row_fwd(Tab<T> tab, Slot slot, int npart_rr, int stride) {
     using G = Geo<T, M, PAD>;
-    constexpr int N = G::N, E = G::ER, P = G::PR, RPW = G::RPW, L = G::L, TT = G::TT;
+    constexpr int N = G::N, E = G::ER, P = G::PR, RPW = G::RPW, L = G::L;
     constexpr int WORDS = G::ROW_WORDS;
     static_assert(NT == G::ROW_THREADS, "row-forward block size");
     __shared__ cx<T> lds[RPW * WORDS];
