@@ -1402,11 +1402,10 @@ __device__ __forceinline__ void row_inv_body(const Tab<T>& tab, const Slot& slot
                         st2<T>(xp, xv);
                     }
             }
-            // the table pointer is laundered so that the compiler reloads the
-            // forward transform's twiddles instead of keeping the inverse
-            // half's loads of the same entries live across both barriers
-            // (163 instead of 118 VGPRs: three workgroups per CU, and the
-            // grid would not be resident as a whole)
+            // the forward transform reads its twiddles afresh (the pointer is
+            // opaque to the compiler) rather than reusing the inverse half's
+            // loads of the same entries across both barriers; the block
+            // index is kept uniform
             Tab<T> tab2 = tab;
             asm volatile("" : "+s"(tab2.tw));
             row_fwd_out<T, M, PAD, NT>(v2, lds, tab2, sd, __builtin_amdgcn_readfirstlane(row0 / RPW));
@@ -1429,7 +1428,9 @@ __global__ void __launch_bounds__(NT) k_row_inv_upd(Tab<T> tab, Slot slot, int s
 
 // One CG iteration's turn in one pass (k_row_inv_upd followed by k_row_fwd):
 // q's row inverse, the folded update, and the next direction's forward row
-// transform, with two grid-wide barriers (tokens token and token + 1).
+// transform, with two grid-wide barriers (tokens token and token + 1).  Four
+// waves per SIMD are asked for: the whole grid must be resident (four
+// 256-thread workgroups per CU at M = 4096), which caps it at 128 VGPRs.
 template <typename T, int M, int PAD, class Slot, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_row_turn(Tab<T> tab, Slot slot, int stride, unsigned long long token) {
