@@ -719,6 +719,15 @@ static void fill_info(fftcg_info* info, const SolveState& st, float ms) {
 // and last check of the chunk before the one in flight.  Until a solve has
 // seen an interval of its own it takes the one the previous solve on the
 // same workspace ended with (solves on one plan tend to be alike).
+// Planned chunks run up to this many nominal chunk lengths while the next
+// check is expected further off: one chunk then covers a whole check
+// interval (about 30 iterations at L = 2048), and each chunk boundary costs
+// a check sequence that exits at once, the launch gap, and with the turn
+// pass a forward and a row-inverse pass in place of one turn.  4 against 2:
+// plain L = 2048 / 1024 / 512 mixed +0.5 / +0.7 / +1.3%, preconditioned
+// L = 2048 / 512 +0.4 / +1.2%, the same iterations and checks.
+constexpr int kChunkSpan = 4;
+
 struct ChunkPlanner {
     int kmax;
     int known_iters = 0;  // iterations at the end of the last chunk the host has seen
@@ -731,8 +740,8 @@ struct ChunkPlanner {
         if (period > 0) {
             const int start = known_iters + k_prev;  // expected start of this chunk
             const int due = last_check + period;
-            // up to two nominal chunks while the next check is far off
-            k = due > start ? std::min(2 * kmax, due - start) : 2;
+            // up to kChunkSpan nominal chunks while the next check is far off
+            k = due > start ? std::min(kChunkSpan * kmax, due - start) : 2;
         }
         k_prev = k;
         return k;
