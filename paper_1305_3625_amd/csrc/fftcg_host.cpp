@@ -740,8 +740,13 @@ struct ChunkPlanner {
         if (period > 0) {
             const int start = known_iters + k_prev;  // expected start of this chunk
             const int due = last_check + period;
-            // up to kChunkSpan nominal chunks while the next check is far off
-            k = due > start ? std::min(kChunkSpan * kmax, due - start) : 2;
+            // up to kChunkSpan nominal chunks while the next check is far
+            // off.  A check due once `due` iterations are done is decided by
+            // the forward pass of iteration `due`, so the chunk takes that
+            // iteration in: it pauses there and the check sequence after the
+            // chunk runs the check (ending before it left the decision to a
+            // further chunk: plain +0.2 to +0.5%, preconditioned +1.4 to +4%)
+            k = due > start ? std::min(kChunkSpan * kmax, due - start + 1) : 2;
         }
         k_prev = k;
         return k;
