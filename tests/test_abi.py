@@ -162,3 +162,18 @@ def test_every_entry_point_catches_exceptions():
             assert src[i + 1:i + 40].lstrip().startswith("FFTCG_ABI_CATCH"), m.group(1)
     declared = [s for s in header_symbols() if s not in ("fftcg_strerror", "fftcg_version")]
     assert sorted(found) == sorted(declared)
+
+
+def test_header_constants_match_binding():
+    """Every integer constant the header defines (status codes, precisions,
+    engines, preconditioners, grid-sync states) has the binding's constant of
+    the same name (without the FFTCG_ prefix) and the same value, and the
+    status names cover every status code."""
+    with open(os.path.join(ROOT, "include", "fftcg.h")) as f:
+        defs = dict(re.findall(r"^#define FFTCG_([A-Z0-9_]+)\s+(-?\d+)\b", f.read(), re.M))
+    assert len(defs) == 23  # 11 status codes, 2 precisions, 3 engines, 2 preconditioners, 5 grid states
+    for name, val in defs.items():
+        assert hasattr(binding, name), name
+        assert getattr(binding, name) == int(val), (name, getattr(binding, name), val)
+    codes = {int(v) for k, v in defs.items() if k == "OK" or k == "PENDING" or k.startswith("E")}
+    assert codes == set(binding.STATUS_NAMES)
