@@ -134,10 +134,11 @@ bool iter_grid_fn(int prec, const PlanTabs& pt, const SlotDesc* slot, int stride
 
 // The turn pass saves the reads of r and p and one launch per iteration but
 // adds a second barrier.  Measured against the folded update alone (whole
-// solves, alternating in one process): L = 2048 mixed +4.2%, L = 256 +2.2%,
-// L = 512 +0.5%, padded L = 512 FP64 +1.9%, but L = 1024 (this M = 2048
-// grid) -1.2%, so it is not offered there.
-constexpr bool kTurnPays = M != 2048;
+// mixed solves, alternating in one process): padded L = 2048 +4.2%, L = 256
+// +2.2%, L = 512 +0.5%, padded L = 512 FP64 +1.9%, periodic M = 256 / 512 /
+// 2048 +1.2 / +2.4 / +5.2%; but padded L = 1024 (M = 2048) -1.2% and
+// periodic M = 1024 -0.7%, so it is not offered on those two grids.
+constexpr bool kTurnPays = PAD ? M != 2048 : M != 1024;
 // Built where its grid can be resident at once: not in FP64 on rows of 16
 // pairs a thread and more (over 200 VGPRs, two workgroups per CU).
 template <typename W>
